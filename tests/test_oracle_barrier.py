@@ -1,0 +1,171 @@
+"""Pins for the oracle's barrier rows (eqs. (16)-(18), (9)).
+
+1. The oracle's hhat, its state gradient and its time partial agree with an
+   independent sympy derivation from the definitions (symbolic_ref.py).
+2. Gradients agree with central finite differences of the oracle's own hhat.
+3. hd and hdd are the time derivatives of h along the exact (fine-step RK4)
+   flow of the drift, for static and moving obstacles.
+4. The rows Lf, g and the h_eps guard match the definitions of eq. (9).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2508_05773_amd import workloads as W
+from tests import symbolic_ref as SR
+
+
+def _rand_state(rng):
+    x = np.array([rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-2, 2), rng.uniform(-1, 1),
+                  rng.uniform(-3, 3), 0.0, rng.uniform(-0.5, 0.5), rng.uniform(0, 5)])
+    x[5] = x[4] + rng.uniform(-0.6, 0.6)
+    return x
+
+
+def _rand_obs(rng, moving=True):
+    return [rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(0.3, 2.5), rng.uniform(0.3, 2.5),
+            rng.uniform(-math.pi, math.pi), 2.0,
+            rng.uniform(-1.5, 1.5) if moving else 0.0, rng.uniform(-1.5, 1.5) if moving else 0.0]
+
+
+def test_obstacle_barrier_matches_symbolic(orc):
+    F = SR.obstacle_funcs()
+    rng = np.random.default_rng(0)
+    prm = W.make_params(0.05)
+    for _ in range(60):
+        x, o, tt = _rand_state(rng), _rand_obs(rng), rng.uniform(0, 3)
+        B = orc.obstacle_barrier(x, tt, o, prm)
+        args = SR.obstacle_args(x, tt, prm, o)
+        for k in ("h", "hd", "hdd", "hhat"):
+            assert B[k] == pytest.approx(F[k](*args), rel=1e-11, abs=1e-11), k
+        for i in range(8):
+            assert B["grad"][i] == pytest.approx(F["grad"][i](*args), rel=1e-10, abs=1e-10), i
+        assert B["dt"] == pytest.approx(F["dt"](*args), rel=1e-10, abs=1e-10)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_hitch_barrier_matches_symbolic(orc, sign):
+    F = SR.hitch_funcs(sign)
+    rng = np.random.default_rng(1)
+    prm = W.make_params(0.1)
+    for _ in range(60):
+        x = _rand_state(rng)
+        B = orc.hitch_barrier(x, sign, prm)
+        args = SR.hitch_args(x, prm)
+        for k in ("h", "hd", "hhat"):
+            assert B[k] == pytest.approx(F[k](*args), rel=1e-12, abs=1e-12), k
+        for i in range(8):
+            assert B["grad"][i] == pytest.approx(F["grad"][i](*args), rel=1e-11, abs=1e-12), i
+        assert B["dt"] == 0.0
+
+
+def test_barrier_gradients_finite_difference(orc):
+    rng = np.random.default_rng(2)
+    prm = W.make_params(0.05)
+    eps = 1e-6
+    for _ in range(40):
+        x, o, tt = _rand_state(rng), _rand_obs(rng), rng.uniform(0, 3)
+        B = orc.obstacle_barrier(x, tt, o, prm)
+        for i in range(8):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += eps
+            xm[i] -= eps
+            fd = (orc.obstacle_barrier(xp, tt, o, prm)["hhat"] - orc.obstacle_barrier(xm, tt, o, prm)["hhat"]) / (2 * eps)
+            assert B["grad"][i] == pytest.approx(fd, rel=1e-6, abs=1e-7), i
+        fd = (orc.obstacle_barrier(x, tt + eps, o, prm)["hhat"] - orc.obstacle_barrier(x, tt - eps, o, prm)["hhat"]) / (2 * eps)
+        assert B["dt"] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+        for sgn in (1, -1):
+            H = orc.hitch_barrier(x, sgn, prm)
+            for i in range(8):
+                xp, xm = x.copy(), x.copy()
+                xp[i] += eps
+                xm[i] -= eps
+                fd = (orc.hitch_barrier(xp, sgn, prm)["hhat"] - orc.hitch_barrier(xm, sgn, prm)["hhat"]) / (2 * eps)
+                assert H["grad"][i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def _rk4_flow(orc, x, prm, dt, n):
+    """integrate the drift (inputs zero) with RK4; returns states at k*dt"""
+    out = [x.copy()]
+    for _ in range(n):
+        k1 = orc.drift(x, prm)
+        k2 = orc.drift(x + 0.5 * dt * k1, prm)
+        k3 = orc.drift(x + 0.5 * dt * k2, prm)
+        k4 = orc.drift(x + dt * k3, prm)
+        x = x + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        out.append(x.copy())
+    return out
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_barrier_time_derivatives_along_flow(orc, moving):
+    rng = np.random.default_rng(3 + moving)
+    prm = W.make_params(0.05)
+    dt = 1e-3
+    for _ in range(10):
+        x, o, t0 = _rand_state(rng), _rand_obs(rng, moving), rng.uniform(0, 2)
+        fwd = _rk4_flow(orc, x, prm, dt, 2)
+        bwd = _rk4_flow(orc, x, prm, -dt, 2)
+        hs = {}
+        for k, xs in ((1, fwd[1]), (2, fwd[2]), (-1, bwd[1]), (-2, bwd[2]), (0, x)):
+            hs[k] = orc.obstacle_barrier(xs, t0 + k * dt, o, prm)["h"]
+        hd_fd = (-hs[2] + 8 * hs[1] - 8 * hs[-1] + hs[-2]) / (12 * dt)
+        hdd_fd = (-hs[2] + 16 * hs[1] - 30 * hs[0] + 16 * hs[-1] - hs[-2]) / (12 * dt * dt)
+        B = orc.obstacle_barrier(x, t0, o, prm)
+        assert B["hd"] == pytest.approx(hd_fd, rel=1e-6, abs=1e-7)
+        assert B["hdd"] == pytest.approx(hdd_fd, rel=1e-4, abs=1e-5)
+        assert B["hhat"] == pytest.approx(B["h"] + prm["Ts"] * B["hd"] + 0.5 * prm["Ts"] ** 2 * B["hdd"], rel=1e-14)
+        for sgn in (1, -1):
+            hh = {k: orc.hitch_barrier(xs, sgn, prm)["h"] for k, xs in ((1, fwd[1]), (2, fwd[2]), (-1, bwd[1]), (-2, bwd[2]))}
+            hd_fd = (-hh[2] + 8 * hh[1] - 8 * hh[-1] + hh[-2]) / (12 * dt)
+            assert orc.hitch_barrier(x, sgn, prm)["hd"] == pytest.approx(hd_fd, rel=1e-6, abs=1e-8)
+
+
+def test_rows_match_definition(orc):
+    """Lf = Ts (L hhat), g = Ts (d hhat/da, d hhat/d delta), in the order
+    obstacles, hitch(+), hitch(-); hh is hhat guarded by h_eps."""
+    Fo = SR.obstacle_funcs()
+    Fp, Fm = SR.hitch_funcs(1), SR.hitch_funcs(-1)
+    rng = np.random.default_rng(5)
+    prob = W.random_small(1, n_obs=4)
+    prm = prob.params
+    for _ in range(20):
+        x, tt = _rand_state(rng), rng.uniform(0, 2)
+        hraw, hh, G, Lf = orc.rows(prob, x, tt)
+        assert len(hh) == prob.n_obs + 2
+        for i, o in enumerate(prob.obstacles):
+            args = SR.obstacle_args(x, tt, prm, o)
+            assert hraw[i] == pytest.approx(Fo["hhat"](*args), rel=1e-11, abs=1e-12)
+            assert Lf[i] == pytest.approx(Fo["Lf"](*args), rel=1e-10, abs=1e-11)
+            assert G[i, 0] == pytest.approx(Fo["g0"](*args), rel=1e-10, abs=1e-13)
+            assert G[i, 1] == pytest.approx(Fo["g1"](*args), rel=1e-10, abs=1e-13)
+        for F, i in ((Fp, prob.n_obs), (Fm, prob.n_obs + 1)):
+            args = SR.hitch_args(x, prm)
+            assert hraw[i] == pytest.approx(F["hhat"](*args), rel=1e-12, abs=1e-13)
+            assert Lf[i] == pytest.approx(F["Lf"](*args), rel=1e-11, abs=1e-13)
+            assert G[i, 0] == pytest.approx(F["g0"](*args), rel=1e-12, abs=1e-14)
+            assert G[i, 1] == pytest.approx(F["g1"](*args), rel=1e-11, abs=1e-14)
+        big = np.abs(hraw) >= prm["h_eps"]
+        assert np.array_equal(hh[big], hraw[big])
+    # hitch-off drops the two hitch rows
+    hraw, hh, G, Lf = orc.rows(prob, _rand_state(rng), 0.0, flags=W.FLAG_HITCH_OFF)
+    assert len(hh) == prob.n_obs
+
+
+def test_h_eps_guard(orc):
+    """hhat inside (-h_eps, h_eps) is pushed to +-h_eps, zero to +h_eps."""
+    prm = W.make_params(0.05)
+    prm["kappa"] = 0.0
+    # hitch row: hhat = dth_max - (th2 - th1) + Ts*(...) ; at v = a = 0 this is dth_max - (th2-th1)
+    x = np.zeros(8)
+    prob = W.Problem(S=1, T=1, x0=x.astype(np.float32), u_nom=np.zeros((1, 3), np.float32),
+                     obstacles=np.zeros((0, 8), np.float32), path=np.zeros((2, 4), np.float32),
+                     ds=0.1, params=prm)
+    dmax = prm["dtheta_max"]
+    for off, want in ((0.0, prm["h_eps"]), (3e-6, prm["h_eps"]), (-3e-6, -prm["h_eps"]), (0.5, 0.5)):
+        xx = x.copy()
+        xx[5] = dmax - off        # h(+) = dmax - (th2 - th1) = off
+        hraw, hh, _, _ = orc.rows(prob, xx, 0.0)
+        assert hraw[0] == pytest.approx(off, abs=1e-15)
+        assert hh[0] == pytest.approx(want, rel=1e-12, abs=1e-18)
