@@ -52,8 +52,10 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
   out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
 }
 
-/* top 24 bits, centred: (r>>8 + 1/2) / 2^24, never 0 or 1 */
-double orc_uniform24(uint32_t r) { return ((double)(r >> 8) + 0.5) / 16777216.0; }
+/* top 23 bits, centred: (r>>9 + 1/2) / 2^23, never 0 or 1.  23 bits keep the
+ * value exactly representable in single precision, so an FP32 implementation
+ * draws bit-identical uniforms. */
+double orc_uniform23(uint32_t r) { return ((double)(r >> 9) + 0.5) / 8388608.0; }
 
 /* Normals eps[0..K) of sample s at step tau: normal k comes from Philox block
  * k/4 with counter (s, tau, k/4, instance), key (seed lo, seed hi); within a
@@ -65,7 +67,7 @@ void orc_normals(uint64_t seed, uint32_t instance, uint32_t s, uint32_t tau, int
     uint32_t r[4];
     orc_philox4x32_10(ctr, key, r);
     double u[4];
-    for (int i = 0; i < 4; ++i) u[i] = orc_uniform24(r[i]);
+    for (int i = 0; i < 4; ++i) u[i] = orc_uniform23(r[i]);
     double n[4];
     double rad0 = sqrt(-2.0 * log(u[0]));
     double rad1 = sqrt(-2.0 * log(u[2]));

@@ -52,7 +52,7 @@ typedef struct {
 } orc_barrier;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-double orc_uniform24(uint32_t r);
+double orc_uniform23(uint32_t r);
 void orc_normals(uint64_t seed, uint32_t instance, uint32_t s, uint32_t tau, int K, double* eps);
 
 void orc_drift(const double x[8], const orc_params* p, double f[8]);

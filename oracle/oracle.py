@@ -70,8 +70,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         D, P, U32, U64, I = C.c_double, C.POINTER(C.c_double), C.c_uint32, C.c_uint64, C.c_int
         L.orc_philox4x32_10.argtypes = [C.POINTER(U32), C.POINTER(U32), C.POINTER(U32)]
-        L.orc_uniform24.argtypes = [U32]
-        L.orc_uniform24.restype = D
+        L.orc_uniform23.argtypes = [U32]
+        L.orc_uniform23.restype = D
         L.orc_normals.argtypes = [U64, U32, U32, U32, I, P]
         L.orc_drift.argtypes = [P, C.POINTER(Params), P]
         L.orc_step.argtypes = [P, P, C.POINTER(Params), P]
@@ -214,8 +214,8 @@ def normals(seed, instance, s, tau, K):
     return e
 
 
-def uniform24(r):
-    return lib().orc_uniform24(int(r) & 0xFFFFFFFF)
+def uniform23(r):
+    return lib().orc_uniform23(int(r) & 0xFFFFFFFF)
 
 
 def step(x, u, params):

@@ -80,12 +80,16 @@ def test_philox_matches_rocrand(orc, rocrand_bin):
     assert n_checked > 300
 
 
-def test_uniform24_exact(orc):
-    assert orc.uniform24(0) == 2.0 ** -25
-    assert orc.uniform24(0xFFFFFFFF) == 1.0 - 2.0 ** -25
-    assert orc.uniform24(0x80000000) == 0.5 + 2.0 ** -25
-    # the low 8 bits are discarded
-    assert orc.uniform24(0x12345600) == orc.uniform24(0x123456FF)
+def test_uniform23_exact(orc):
+    assert orc.uniform23(0) == 2.0 ** -24
+    assert orc.uniform23(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    assert orc.uniform23(0x80000000) == 0.5 + 2.0 ** -24
+    # the low 9 bits are discarded, and every value is a float32
+    assert orc.uniform23(0x12345600) == orc.uniform23(0x123457FF)
+    rng = np.random.default_rng(0)
+    for r in rng.integers(0, 2**32, size=1000, dtype=np.uint64):
+        u = orc.uniform23(int(r))
+        assert float(np.float32(u)) == u and 0.0 < u < 1.0
 
 
 def test_normal_block_layout(orc):
@@ -94,7 +98,7 @@ def test_normal_block_layout(orc):
     e = orc.normals(seed, inst, 5, 9, 11)
     for b in range(3):
         r = orc.philox([5, 9, b, inst], [seed & 0xFFFFFFFF, seed >> 32])
-        u = [orc.uniform24(v) for v in r]
+        u = [orc.uniform23(v) for v in r]
         rad0 = math.sqrt(-2 * math.log(u[0]))
         rad1 = math.sqrt(-2 * math.log(u[2]))
         blk = [rad0 * math.cos(2 * math.pi * u[1]), rad0 * math.sin(2 * math.pi * u[1]),
