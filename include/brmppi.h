@@ -1,0 +1,231 @@
+/*
+ * brmppi.h -- C ABI of the MI355X (gfx950) BR-MPPI control-update library.
+ *
+ * One call computes one control update of Barrier-Rate guided MPPI for a
+ * kinematic tractor-trailer (arXiv 2508.05773): S perturbed input sequences
+ * over a horizon T are rolled out through eq. (6) while every step is
+ * projected onto the barrier-rate equalities of eq. (9) with the soft-bound
+ * closed form of eqs. (11)-(12); the contouring cost of eqs. (13)-(15) is
+ * accumulated; the new nominal sequence is the exponentially weighted average
+ * of the applied sequences (Sec. III-B, eq. (5)).
+ *
+ * All device work runs in the library's HIP kernels.  The caller provides the
+ * device memory (an arena, e.g. a torch uint8 tensor) and the HIP streams; the
+ * library sub-allocates from the arena and never calls hipMalloc.
+ *
+ * Conventions
+ *  - All pointers in the problem / outputs structs are HOST pointers unless
+ *    the field says otherwise.  The caller owns every host buffer; inputs are
+ *    copied before the call returns.  Output buffers are written only when the
+ *    call returns BRMPPI_OK (or BRMPPI_ENONFINITE, see below).
+ *  - Return codes: 0 = success, >0 = pending, <0 = error.  No C++ exception
+ *    crosses the ABI.  An invalid argument leaves the library state unchanged.
+ *    brmppi_last_error() returns a thread-local message for the last error.
+ *  - Layouts are row-major float32: a sequence is [T][3] with columns
+ *    (jerk, steer rate, progress rate); a path is [n][4] with columns
+ *    (x, y, theta1_ref, theta2_ref) sampled every ds metres of arc length.
+ *  - Threading: one context may be used from one application thread; the
+ *    served form (submit/poll) adds one internal request thread per context.
+ */
+#ifndef BRMPPI_H
+#define BRMPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define BRMPPI_OK 0
+#define BRMPPI_PENDING 1          /* poll: the ticket is still in flight */
+#define BRMPPI_EINVAL (-1)        /* invalid argument; nothing changed */
+#define BRMPPI_ENOMEM (-2)        /* does not fit in the arena */
+#define BRMPPI_EAGAIN (-3)        /* served form: request queue full, retry */
+#define BRMPPI_ENONFINITE (-4)    /* every rollout cost was NaN/Inf: the nominal
+                                     sequence is returned, warm start untouched */
+#define BRMPPI_ENOTICKET (-5)     /* unknown or already consumed ticket */
+#define BRMPPI_EDEVICE (-6)       /* a HIP call failed */
+#define BRMPPI_ETIMEDOUT (-7)     /* brmppi_wait deadline passed */
+#define BRMPPI_ESTATE (-8)        /* missing state (no path / no warm start) */
+
+/* ---- limits ------------------------------------------------------------- */
+#define BRMPPI_MAX_OBS 32         /* obstacles per solve */
+#define BRMPPI_MAX_T 512          /* horizon */
+#define BRMPPI_MAX_S (1u << 22)   /* samples per solve */
+#define BRMPPI_MAX_PATH (1u << 20)/* waypoints per path */
+#define BRMPPI_MAX_BATCH 1024     /* instances per brmppi_solve_batch */
+
+/* ---- problem flags ------------------------------------------------------ */
+#define BRMPPI_GUIDANCE_OFF 1u    /* plain MPPI: sampled inputs applied unprojected */
+#define BRMPPI_HITCH_OFF 2u       /* no hitch-angle rows (N_c = n_obs) */
+#define BRMPPI_X0_RESIDENT 4u     /* start from the controller's device-resident plant
+                                     state (brmppi_set_state / brmppi_closed_loop) */
+
+/* ---- context flags ------------------------------------------------------ */
+#define BRMPPI_CTX_PROFILE 1u     /* time every kernel with HIP events */
+
+typedef struct brmppi_ctx brmppi_ctx;
+
+typedef struct {
+  void* arena;                /* DEVICE memory, >= 256-byte aligned, owned by the caller,
+                                 must outlive the context */
+  size_t arena_bytes;
+  void* streams[4];           /* hipStream_t handles (default priority); streams[0] runs the
+                                 blocking calls, all of them serve submit/poll batches */
+  uint32_t n_streams;         /* 1..4 */
+  uint32_t max_controllers;   /* controller slots (resident path + warm start each) */
+  uint32_t max_inflight;      /* served form: queued + running requests (0 = 4096) */
+  const char* autotune_cache; /* JSON launch-shape cache path, or NULL */
+  uint32_t flags;             /* BRMPPI_CTX_* */
+  int32_t device;             /* HIP device ordinal of the arena and streams */
+} brmppi_config;
+
+/* Tuning parameters (all SI units).  Groups:
+ *  vehicle, eq. (6) / (18):   Ts, l1 (wheelbase), lh (hitch offset), l2 (trailer
+ *                              length), dtheta_max, kappa (hitch limit dtheta_max -
+ *                              kappa v), r_disc (footprint disc radius, eq. (16))
+ *  contouring, eq. (13):      Qc, Ql, Qth1, Qth2, R_j, R_w, mu, nu_bar
+ *  projection, eq. (11):      W_j, W_w, W_a (diagonal weight W), rho,
+ *                              input bounds [j_lo, j_hi], [w_lo, w_hi]
+ *  barrier rates, eq. (9):    alpha0 (initial rate of every row), soft bounds
+ *                              [alpha_lo, alpha_hi] on the next rate
+ *  sampling (Sec. III-B):     sigma_j, sigma_w, sigma_nu (input noise),
+ *                              sigma_a (auxiliary-input noise)
+ *  guard:                     h_eps (|hhat| floor in each row) */
+typedef struct {
+  float Ts, l1, lh, l2, dtheta_max, kappa, r_disc;
+  float Qc, Ql, Qth1, Qth2, R_j, R_w, mu, nu_bar;
+  float W_j, W_w, W_a, rho, j_lo, j_hi, w_lo, w_hi;
+  float alpha0, alpha_lo, alpha_hi, sigma_j, sigma_w, sigma_nu, sigma_a;
+  float h_eps;
+} brmppi_params;
+
+/* Obstacle (Sec. IV-C, eq. (16)): centre (cx, cy) at t = 0, semi-axes (mx, my),
+ * orientation heading, exponent e (only e == 2 is implemented), constant
+ * velocity (vx, vy) for the prediction of Assumption 2. */
+typedef struct { float cx, cy, mx, my, heading, e, vx, vy; } brmppi_obstacle;
+
+/* One control update (the finite-horizon problem of eq. (8) plus MPPI inputs). */
+typedef struct {
+  uint32_t controller;        /* slot owning the resident path and warm start */
+  uint32_t S, T;              /* samples (1..BRMPPI_MAX_S), horizon (1..BRMPPI_MAX_T) */
+  float x0[8];                /* px, py, v, a, theta1, theta2, delta, psi (ignored with
+                                 BRMPPI_X0_RESIDENT) */
+  const float* u_nom;         /* T*3 nominal sequence, or NULL = the controller's resident
+                                 warm start (the shifted result of its last update) */
+  const brmppi_obstacle* obs; /* n_obs records */
+  uint32_t n_obs;             /* 0..BRMPPI_MAX_OBS */
+  float t0;                   /* time of x0 for moving obstacles */
+  float lambda;               /* temperature of the weights, > 0 */
+  uint64_t seed;              /* Philox key */
+  uint32_t instance;          /* Philox counter word 3 */
+  uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT */
+  const brmppi_params* params;/* required */
+} brmppi_problem;
+
+typedef struct {
+  float J_min;                /* min_s J_s */
+  float Z;                    /* sum_s exp(-(J_s - J_min)/lambda) */
+  float ess;                  /* effective sample size 1/sum wbar^2 */
+  int32_t status;             /* BRMPPI_OK or BRMPPI_ENONFINITE */
+  double latency_us;          /* submit/solve entry to result ready (host clock) */
+} brmppi_stats;
+
+/* Optional extra outputs of brmppi_solve_ex (host buffers; NULL = skip). */
+typedef struct {
+  float* u_out;               /* T*3 new nominal sequence (eq. (5)) -- required */
+  float* J_out;               /* S rollout costs, +inf where non-finite */
+  float* useq_out;            /* 3*T*S applied inputs, layout [t][k][s] */
+} brmppi_outputs;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+/* Create a context over a caller-owned device arena.  Errors: EINVAL (NULL or
+ * misaligned arena, n_streams outside 1..4, max_controllers 0), EDEVICE. */
+int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out);
+/* Drain in-flight work, stop the request thread, free host resources.  The
+ * arena is the caller's and is not touched afterwards. */
+int brmppi_destroy(brmppi_ctx* ctx);
+const char* brmppi_last_error(void);
+
+/* ---- controller state --------------------------------------------------- */
+/* Copy a reference path zeta(psi) (Sec. IV-B) into the controller's device
+ * slot; it stays resident for every later solve of that controller.
+ * path: n*4 host floats, n in 2..BRMPPI_MAX_PATH, ds > 0. */
+int brmppi_set_path(brmppi_ctx* ctx, uint32_t controller, const float* path, uint32_t n, float ds);
+/* Read / replace the resident warm start (the receding-horizon shift of
+ * Sec. III-B).  T*3 host floats. */
+int brmppi_get_nominal(brmppi_ctx* ctx, uint32_t controller, float* u, uint32_t T);
+int brmppi_set_nominal(brmppi_ctx* ctx, uint32_t controller, const float* u, uint32_t T);
+/* Resident FP64 plant state used by BRMPPI_X0_RESIDENT and brmppi_closed_loop. */
+int brmppi_set_state(brmppi_ctx* ctx, uint32_t controller, const double x[8]);
+int brmppi_get_state(brmppi_ctx* ctx, uint32_t controller, double x[8]);
+
+/* ---- plain solve (blocking) --------------------------------------------- */
+/* One control update on streams[0]; returns when u_out holds the new nominal
+ * sequence (T*3).  The controller's warm start becomes the shifted result.
+ * Errors: EINVAL, ESTATE (no path; u_nom NULL without a warm start of length
+ * T), ENOMEM, EDEVICE; ENONFINITE (u_out = nominal sequence). */
+int brmppi_solve(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st);
+int brmppi_solve_ex(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out,
+                    brmppi_stats* st);
+
+/* ---- batched solve (blocking) ------------------------------------------- */
+/* n independent updates (distinct controllers) in one persistent-kernel
+ * launch captured in a HIP graph.  u_outs[i] receives T_i*3 floats; st may be
+ * NULL or an array of n.  Each instance's result equals its plain solve. */
+int brmppi_solve_batch(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n, float* const* u_outs,
+                       brmppi_stats* st);
+
+/* ---- served form (asynchronous, continuous batching) -------------------- */
+/* Queue one update; returns at once with a ticket.  The request thread admits
+ * queued requests as controller slots and arena memory free up and launches
+ * them together with whatever else is pending, overlapping on the device.
+ * Requests of one controller run in submission order.
+ * Errors: EINVAL, ESTATE, EAGAIN (max_inflight reached), ENOMEM (can never fit). */
+int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket);
+/* Non-blocking: BRMPPI_PENDING while in flight; otherwise copies the result
+ * (T*3) and stats, releases the ticket and returns its status. */
+int brmppi_poll(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st);
+/* Blocking variant of poll with a deadline (ETIMEDOUT). */
+int brmppi_wait(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st, uint32_t timeout_ms);
+
+/* ---- closed loop on the device ------------------------------------------ */
+/* n_updates receding-horizon updates of one controller without host round
+ * trips: update k solves from the resident plant state with seed p->seed + k,
+ * then advances the plant by the first averaged input (jerk and steer rate
+ * clamped to [j_lo, j_hi], [w_lo, w_hi]) with eq. (6) in FP64.  x_out
+ * ((n_updates+1)*8 doubles) and u_applied ((n_updates)*3 floats) are optional
+ * host buffers filled at the end.  p->u_nom seeds the first update (NULL =
+ * resident warm start); BRMPPI_X0_RESIDENT is implied. */
+int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_updates, double* x_out,
+                       float* u_applied);
+
+/* ---- launch shapes / profiling ------------------------------------------ */
+/* Time the rollout kernel for each candidate launch shape on synthetic
+ * problems and keep the fastest per constraint bucket; writes the JSON cache
+ * named in the config (if any).  Shapes never change results. */
+int brmppi_autotune(brmppi_ctx* ctx);
+/* Force a rollout launch shape (block size 64..1024, lanes per sample 1, 2, 4
+ * or 8) for every bucket; 0 restores the tuned/default choice. */
+int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t lanes_per_sample);
+/* Kernel timings accumulated under BRMPPI_CTX_PROFILE (ms totals and counts):
+ * out[0..1] rollout, out[2..3] weights, out[4..5] reduce, out[6..7] plant. */
+int brmppi_profile_read(brmppi_ctx* ctx, double out[8]);
+int brmppi_profile_reset(brmppi_ctx* ctx);
+
+/* ---- debug entry points (parity tests) ---------------------------------- */
+/* Philox4x32-10 on the device: n counters (host, n*4) under one key -> n*4
+ * outputs (host). */
+int brmppi_debug_philox(brmppi_ctx* ctx, const uint32_t* ctr, const uint32_t key[2], uint32_t n,
+                        uint32_t* out);
+/* The normals the rollout kernel draws: for each of n (sample, step) pairs
+ * (host, n*2) the first K normals -> out (host, n*K). */
+int brmppi_debug_normals(brmppi_ctx* ctx, uint64_t seed, uint32_t instance, const uint32_t* s_tau,
+                         uint32_t n, uint32_t K, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BRMPPI_H */

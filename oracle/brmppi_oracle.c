@@ -257,12 +257,24 @@ void orc_hitch_barrier(const double x[8], int sign, const orc_params* p, orc_bar
 /*   Lf_i = Ts (grad hhat . f_c + d hhat/dt)   (f = Ts f_c, Sec. III-A)      */
 /*   g_i  = Ts (d hhat/da, d hhat/d delta)     (jerk, steer-rate columns;     */
 /*          the progress-rate column is zero because hhat does not involve psi)*/
-/* Order: obstacles as given, then hitch (+), hitch (-).                      */
+/* Order: hitch (+), hitch (-) (absent with ORC_HITCH_OFF), then the          */
+/* obstacles as given.                                                        */
 /* READING (guard against a singular A M^-1 A'): hhat is replaced by           */
 /* copysign(max(|hhat|, h_eps), hhat), with 0 mapped to +h_eps.                */
 /* ------------------------------------------------------------------------ */
 int orc_num_rows(const orc_problem* pr) {
   return pr->n_obs + ((pr->flags & ORC_HITCH_OFF) ? 0 : 2);
+}
+
+/* Normals drawn per (sample, step): 0..2 perturb (j, omega, nu); 3 and 4 are
+ * the auxiliary inputs of the hitch rows (+, -); 5 + o that of obstacle o.
+ * The numbering does not depend on ORC_HITCH_OFF (3 and 4 are then unused). */
+int orc_num_normals(const orc_problem* pr) { return 5 + pr->n_obs; }
+
+/* normal index of row i in the order produced by orc_rows */
+static int row_normal(const orc_problem* pr, int i) {
+  if (pr->flags & ORC_HITCH_OFF) return 5 + i;
+  return 3 + i;
 }
 
 static void row_from_barrier(const orc_barrier* B, const double f[8], const orc_params* p,
@@ -283,17 +295,17 @@ void orc_rows(const orc_problem* pr, const orc_params* p, const double x[8], dou
   double f[8];
   orc_drift(x, p, f);
   int i = 0;
-  for (int o = 0; o < pr->n_obs; ++o, ++i) {
-    orc_barrier B;
-    orc_obstacle_barrier(x, t, &pr->obs[o], p, &B);
-    row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
-  }
   if (!(pr->flags & ORC_HITCH_OFF)) {
     for (int sgn = 1; sgn >= -1; sgn -= 2, ++i) {
       orc_barrier B;
       orc_hitch_barrier(x, sgn, p, &B);
       row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
     }
+  }
+  for (int o = 0; o < pr->n_obs; ++o, ++i) {
+    orc_barrier B;
+    orc_obstacle_barrier(x, t, &pr->obs[o], p, &B);
+    row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
   }
 }
 
@@ -439,17 +451,18 @@ double orc_terminal_cost(const double x[8], const double* path, int n, double ds
 /* ------------------------------------------------------------------------ */
 /* One rollout (Sec. IV-A, with the MPPI sampling of Sec. III-B).             */
 /* For tau = 0..T-1: draw eps (or take it from `eps`), form                   */
-/*   u_des = u_nom[tau] + sigma * eps[0:3],  u~alpha_i = sigma_a eps[3+i],    */
+/*   u_des = u_nom[tau] + sigma * eps[0:3],  u~alpha_i = sigma_a eps[n(i)]    */
+/*   (n(i) the normal of row i, see orc_num_normals),                          */
 /* project z_des = [j, omega, u~alpha] with eq. (12), apply u* = (j*, w*, nu)  */
 /* (READING: the progress rate is not projected), add r(x_tau, u*_tau),       */
 /* step eq. (6), update alpha_{tau+1} = alpha_tau + u*alpha.                  */
 /* J = sum_tau r + r_N(x_T).  alpha starts at alpha0 for every row.           */
-/* eps, when given, is T*(3+nc) for this sample.                               */
+/* eps, when given, is T*(5+n_obs) for this sample.                            */
 /* ------------------------------------------------------------------------ */
 double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const double* eps,
                    double* useq, double* traj, double* alphas) {
   const int nc = orc_num_rows(pr);
-  const int K = 3 + nc;
+  const int K = orc_num_normals(pr);
   const int guided = !(pr->flags & ORC_GUIDANCE_OFF);
   double x[8];
   memcpy(x, pr->x0, sizeof(x));
@@ -478,7 +491,7 @@ double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const
       for (int i = 0; i < nc; ++i) b[i] = -Lf[i] - alpha[i] * hh[i];
       zd[0] = u[0];
       zd[1] = u[1];
-      for (int i = 0; i < nc; ++i) zd[2 + i] = p->sigma_a * e[3 + i];
+      for (int i = 0; i < nc; ++i) zd[2 + i] = p->sigma_a * e[row_normal(pr, i)];
       orc_project(nc, zd, alpha, hh, G, b, p, zs);
       u[0] = zs[0];
       u[1] = zs[1];
@@ -541,7 +554,7 @@ int orc_weights(const double* J, int S, double lambda, double* wbar, double* m_o
 int orc_solve(const orc_problem* pr, const orc_params* p, int nthreads, const double* eps,
               double* U_new, double* J, double* wbar, double* useq_all, double* stats) {
   const int S = pr->S, T = pr->T;
-  const int K = 3 + orc_num_rows(pr);
+  const int K = orc_num_normals(pr);
   int own = 0;
   if (!useq_all) {
     useq_all = (double*)malloc(sizeof(double) * (size_t)S * T * 3);

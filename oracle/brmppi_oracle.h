@@ -63,6 +63,7 @@ void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, co
 void orc_hitch_barrier(const double x[8], int sign, const orc_params* p, orc_barrier* out);
 
 int orc_num_rows(const orc_problem* pr);
+int orc_num_normals(const orc_problem* pr);
 void orc_rows(const orc_problem* pr, const orc_params* p, const double x[8], double t,
               double* hraw, double* hh, double* G, double* Lf);
 

@@ -79,6 +79,8 @@ def lib():
         L.orc_hitch_barrier.argtypes = [P, I, C.POINTER(Params), C.POINTER(Barrier)]
         L.orc_num_rows.argtypes = [C.POINTER(ProblemC)]
         L.orc_num_rows.restype = I
+        L.orc_num_normals.argtypes = [C.POINTER(ProblemC)]
+        L.orc_num_normals.restype = I
         L.orc_rows.argtypes = [C.POINTER(ProblemC), C.POINTER(Params), P, D, P, P, P, P]
         L.orc_project.argtypes = [I, P, P, P, P, P, C.POINTER(Params), P]
         L.orc_project.restype = I
@@ -145,6 +147,10 @@ class OracleProblem:
     def n_c(self):
         return lib().orc_num_rows(C.byref(self.c))
 
+    @property
+    def n_normals(self):
+        return lib().orc_num_normals(C.byref(self.c))
+
 
 def solve(prob, nthreads=None, eps=None, want_useq=False, **kw):
     """Full update.  Returns dict(U_new (T,3), J (S,), wbar (S,), rc, stats, useq)."""
@@ -159,7 +165,7 @@ def solve(prob, nthreads=None, eps=None, want_useq=False, **kw):
     ep = None
     if eps is not None:
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
-        assert eps.size == S * T * (3 + op.n_c)
+        assert eps.size == S * T * op.n_normals
         ep = _dp(eps)
     rc = lib().orc_solve(C.byref(op.c), C.byref(op.params), int(nthreads), ep, _dp(U), _dp(J), _dp(w),
                          _dp(useq) if useq is not None else None, _dp(st))
@@ -180,7 +186,7 @@ def rollout(prob, s, eps=None, **kw):
     ep = None
     if eps is not None:
         eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
-        assert eps.size == T * (3 + nc)
+        assert eps.size == T * op.n_normals
         ep = _dp(eps)
     J = lib().orc_rollout(C.byref(op.c), C.byref(op.params), int(s), ep, _dp(useq), _dp(traj), _dp(al))
     return J, useq.reshape(T, 3), traj.reshape(T + 1, 8), al[: nc * T].reshape(T, nc)

@@ -124,7 +124,7 @@ def test_barrier_time_derivatives_along_flow(orc, moving):
 
 def test_rows_match_definition(orc):
     """Lf = Ts (L hhat), g = Ts (d hhat/da, d hhat/d delta), in the order
-    obstacles, hitch(+), hitch(-); hh is hhat guarded by h_eps."""
+    hitch(+), hitch(-), obstacles; hh is hhat guarded by h_eps."""
     Fo = SR.obstacle_funcs()
     Fp, Fm = SR.hitch_funcs(1), SR.hitch_funcs(-1)
     rng = np.random.default_rng(5)
@@ -134,13 +134,14 @@ def test_rows_match_definition(orc):
         x, tt = _rand_state(rng), rng.uniform(0, 2)
         hraw, hh, G, Lf = orc.rows(prob, x, tt)
         assert len(hh) == prob.n_obs + 2
-        for i, o in enumerate(prob.obstacles):
+        for o_idx, o in enumerate(prob.obstacles):
+            i = 2 + o_idx
             args = SR.obstacle_args(x, tt, prm, o)
             assert hraw[i] == pytest.approx(Fo["hhat"](*args), rel=1e-11, abs=1e-12)
             assert Lf[i] == pytest.approx(Fo["Lf"](*args), rel=1e-10, abs=1e-11)
             assert G[i, 0] == pytest.approx(Fo["g0"](*args), rel=1e-10, abs=1e-13)
             assert G[i, 1] == pytest.approx(Fo["g1"](*args), rel=1e-10, abs=1e-13)
-        for F, i in ((Fp, prob.n_obs), (Fm, prob.n_obs + 1)):
+        for F, i in ((Fp, 0), (Fm, 1)):
             args = SR.hitch_args(x, prm)
             assert hraw[i] == pytest.approx(F["hhat"](*args), rel=1e-12, abs=1e-13)
             assert Lf[i] == pytest.approx(F["Lf"](*args), rel=1e-11, abs=1e-13)

@@ -69,7 +69,7 @@ def test_bruteforce_s4_t3(orc):
     p = _problem()
     P = {k: mp.mpf(v) for k, v in p.params.items()}
     nc = p.n_obs + 2
-    K = 3 + nc
+    K = 5 + p.n_obs          # normals: 3 inputs, hitch(+), hitch(-), obstacle 0
     rng = np.random.default_rng(11)
     eps = rng.integers(-1, 2, size=(p.S, p.T, K)).astype(np.float64)
     path = [[mp.mpf(float(v)) for v in row] for row in p.path]
@@ -88,7 +88,7 @@ def test_bruteforce_s4_t3(orc):
             tt = mp.mpf(p.t0) + tau * P["Ts"]
             e = [mp.mpf(v) for v in eps[s, tau]]
             u = [mp.mpf(float(p.u_nom[tau, k])) + sig[k] * e[k] for k in range(3)]
-            at = [P["sigma_a"] * e[3 + i] for i in range(nc)]
+            at = [P["sigma_a"] * e[3 + i] for i in range(nc)]   # rows: hitch+, hitch-, obstacle
             # rows
             hh, G, Lf = [], [], []
             oargs = list(x) + [tt, P["Ts"], P["l1"], P["lh"], P["l2"], P["r_disc"]] + \
@@ -96,7 +96,7 @@ def test_bruteforce_s4_t3(orc):
                                             p.obstacles[0, 0], p.obstacles[0, 1], p.obstacles[0, 6],
                                             p.obstacles[0, 7])]
             hargs = list(x) + [P["Ts"], P["l1"], P["lh"], P["l2"], P["dtheta_max"], P["kappa"]]
-            for F, args in ((Fo, oargs), (Fh[1], hargs), (Fh[-1], hargs)):
+            for F, args in ((Fh[1], hargs), (Fh[-1], hargs), (Fo, oargs)):
                 hv = F["hhat"](*args)
                 assert abs(hv) > 1e-3          # the h_eps guard is not exercised here
                 hh.append(hv)
