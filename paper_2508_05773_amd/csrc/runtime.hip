@@ -1,0 +1,1433 @@
+// Host runtime behind the C ABI in include/brmppi.h: arena sub-allocation,
+// controller slots (resident path, warm start, plant state), the plain,
+// batched (persistent kernels in a HIP graph) and closed-loop solves, and the
+// served form (a request thread doing continuous batching over the streams).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "brmppi_internal.h"
+
+using namespace brm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                            \
+  do {                                                                                       \
+    hipError_t e_ = (x);                                                                     \
+    if (e_ != hipSuccess) return fail(BRMPPI_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+using Clock = std::chrono::steady_clock;
+
+// ---------------------------------------------------------------------------
+// first-fit sub-allocator over the caller's device arena
+// ---------------------------------------------------------------------------
+struct Block {
+  char* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+class Arena {
+ public:
+  void init(void* base, size_t bytes) {
+    base_ = static_cast<char*>(base);
+    size_ = bytes;
+    free_.clear();
+    free_[0] = bytes;
+  }
+  Block alloc(size_t n) {
+    n = round_up(std::max<size_t>(n, 1), 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        used_ += n;
+        return Block{base_ + off, n};
+      }
+    }
+    return Block{};
+  }
+  void release(Block& b) {
+    if (!b.ptr) return;
+    size_t off = (size_t)(b.ptr - base_), len = b.bytes;
+    used_ -= len;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        b = Block{};
+        return;
+      }
+    }
+    free_[off] = len;
+    b = Block{};
+  }
+  bool fits(size_t n) const {
+    n = round_up(std::max<size_t>(n, 1), 256);
+    for (auto& kv : free_)
+      if (kv.second >= n) return true;
+    return false;
+  }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+// pinned host staging buffer
+struct Pinned {
+  char* ptr = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t n) {
+    if (n <= bytes) return 0;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    n = round_up(std::max<size_t>(n, 4096), 4096);
+    HIPCHK(hipHostMalloc((void**)&ptr, n, hipHostMallocDefault));
+    bytes = n;
+    return 0;
+  }
+  void release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+};
+
+struct Controller {
+  Block mem;                  // unom (3*MAX_T floats) + plant (8 doubles)
+  float* unom = nullptr;
+  double* plant = nullptr;
+  Block path_blk;
+  float4* path = nullptr;
+  uint32_t n_path = 0;
+  float ds = 0.0f;
+  uint32_t warm_T = 0;        // length of the resident warm start, 0 = none
+  bool plant_set = false;
+  bool busy = false;          // a served request is in flight
+};
+
+// layout of one instance's scratch inside a block
+struct ScratchLayout {
+  size_t off_ustar, off_J, off_gam, off_wpart, off_rpart, off_counter, off_out, bytes;
+  uint32_t S_pad, n_wchunk, n_rgroup;
+};
+
+ScratchLayout scratch_layout(uint32_t S, uint32_t T) {
+  ScratchLayout L;
+  L.S_pad = (uint32_t)round_up(S, 256);
+  L.n_wchunk = (S + kWChunk - 1) / kWChunk;
+  L.n_rgroup = (3 * T + kRowsPerBlock - 1) / kRowsPerBlock;
+  size_t o = 0;
+  L.off_ustar = o;
+  o = round_up(o + (size_t)3 * T * L.S_pad * sizeof(float), 256);
+  L.off_J = o;
+  o = round_up(o + (size_t)L.S_pad * sizeof(float), 256);
+  L.off_gam = o;
+  o = round_up(o + (size_t)L.S_pad * sizeof(float), 256);
+  L.off_wpart = o;
+  o = round_up(o + (size_t)L.n_wchunk * sizeof(float4), 256);
+  L.off_rpart = o;
+  o = round_up(o + (size_t)L.n_wchunk * 3 * T * sizeof(float), 256);
+  L.off_counter = o;
+  o = round_up(o + 16, 256);
+  L.off_out = o;  // stats[4] + u_new[3T]
+  o = round_up(o + (size_t)(4 + 3 * T) * sizeof(float), 256);
+  L.bytes = o;
+  return L;
+}
+
+struct Profile {
+  double ms[4] = {0, 0, 0, 0};
+  double n[4] = {0, 0, 0, 0};
+};
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t a, b;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  brmppi_problem prob{};
+  brmppi_params params{};
+  std::vector<brmppi_obstacle> obs;
+  std::vector<float> unom;
+  std::vector<float> result;
+  brmppi_stats st{};
+  int status = BRMPPI_PENDING;
+  bool done = false;
+  Clock::time_point t_submit;
+  Block scratch;
+};
+
+struct ServedBatch {
+  std::vector<Request*> reqs;
+  Block mem;              // descs + tiles + items + per-instance scratch
+  size_t out_off = 0;     // device offset of the packed outputs inside mem
+  std::vector<size_t> out_pos;  // float offset of each request's [stats(4) | u(3T)]
+  size_t out_floats = 0;
+  int slot = 0;
+  hipEvent_t done_ev = nullptr;
+};
+
+struct LaunchShape {
+  uint32_t block = 128;
+  uint32_t lanes = 1;
+};
+
+}  // namespace
+
+struct brmppi_ctx {
+  int device = 0;
+  Arena arena;
+  hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint32_t n_streams = 1;
+  uint32_t max_inflight = 4096;
+  uint32_t flags = 0;
+  int n_cu = 256;
+  std::string tune_path;
+  std::vector<Controller> ctrl;
+  LaunchShape shape[33];        // indexed by bucket
+  LaunchShape forced;           // block 0 = not forced
+  Block counters_blk;           // BatchCounters per stream + spare
+  BatchCounters* counters = nullptr;
+
+  // blocking-path scratch (cached)
+  Block scratch;
+  Pinned pin;                   // blocking staging
+  // graph cache for the batched form
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<uint64_t> graph_key;
+  // profiling
+  Profile prof;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedLaunch> pending_timing;
+
+  // served form
+  std::mutex mu;                // guards everything below and every device enqueue
+  std::condition_variable cv;
+  std::thread loop;
+  bool running = false;
+  uint64_t next_ticket = 1;
+  std::deque<Request*> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::vector<ServedBatch> inflight;
+  Pinned slot_pin[4];
+  bool slot_busy[4] = {false, false, false, false};
+  size_t n_active = 0;          // queued + running requests
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+bool finite_params(const brmppi_params& p) {
+  const float* f = reinterpret_cast<const float*>(&p);
+  for (size_t i = 0; i < sizeof(p) / sizeof(float); ++i)
+    if (!std::isfinite(f[i])) return false;
+  return true;
+}
+
+int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
+  if (!ctx || !p) return fail(BRMPPI_EINVAL, "null context or problem");
+  if (p->controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  if (p->S < 1 || p->S > BRMPPI_MAX_S) return fail(BRMPPI_EINVAL, "S out of range");
+  if (p->T < 1 || p->T > BRMPPI_MAX_T) return fail(BRMPPI_EINVAL, "T out of range");
+  if (p->n_obs > BRMPPI_MAX_OBS) return fail(BRMPPI_EINVAL, "too many obstacles");
+  if (p->n_obs > 0 && !p->obs) return fail(BRMPPI_EINVAL, "obstacles pointer is NULL");
+  if (!p->params) return fail(BRMPPI_EINVAL, "params pointer is NULL");
+  if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT))
+    return fail(BRMPPI_EINVAL, "unknown flags");
+  const brmppi_params& P = *p->params;
+  if (!finite_params(P)) return fail(BRMPPI_EINVAL, "non-finite parameter");
+  if (!(P.Ts > 0) || !(P.l1 > 0) || !(P.l2 > 0) || !(P.h_eps > 0))
+    return fail(BRMPPI_EINVAL, "Ts, l1, l2 and h_eps must be positive");
+  if (!(P.W_j + P.rho > 0) || !(P.W_w + P.rho > 0) || !(P.W_a + P.rho > 0) || P.rho < 0 || P.W_j < 0 ||
+      P.W_w < 0 || P.W_a < 0)
+    return fail(BRMPPI_EINVAL, "projection weights must be >= 0 with W + rho > 0");
+  if (!(p->lambda > 0) || !std::isfinite(p->lambda)) return fail(BRMPPI_EINVAL, "lambda must be positive");
+  if (!std::isfinite(p->t0)) return fail(BRMPPI_EINVAL, "t0 must be finite");
+  for (uint32_t i = 0; i < p->n_obs; ++i) {
+    const brmppi_obstacle& o = p->obs[i];
+    if (o.e != 2.0f) return fail(BRMPPI_EINVAL, "only e == 2 obstacles are implemented");
+    const float v[8] = {o.cx, o.cy, o.mx, o.my, o.heading, o.e, o.vx, o.vy};
+    for (float x : v)
+      if (!std::isfinite(x)) return fail(BRMPPI_EINVAL, "non-finite obstacle field");
+    if (!(o.mx + P.r_disc > 0) || !(o.my + P.r_disc > 0))
+      return fail(BRMPPI_EINVAL, "inflated semi-axes must be positive");
+  }
+  const Controller& c = ctx->ctrl[p->controller];
+  if (!c.path) return fail(BRMPPI_ESTATE, "controller has no path (brmppi_set_path)");
+  if (!p->u_nom && c.warm_T != p->T)
+    return fail(BRMPPI_ESTATE, "no resident warm start of length T for this controller");
+  if ((p->flags & BRMPPI_X0_RESIDENT) && !c.plant_set)
+    return fail(BRMPPI_ESTATE, "no resident plant state (brmppi_set_state)");
+  return BRMPPI_OK;
+}
+
+void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const ScratchLayout& L, char* base,
+               uint32_t seed_offset) {
+  std::memset(&d, 0, sizeof(d));
+  d.prm = *p.params;
+  d.lambda = p.lambda;
+  d.inv_lambda = 1.0f / p.lambda;
+  for (int k = 0; k < 8; ++k) d.x0[k] = p.x0[k];
+  d.t0 = p.t0;
+  d.ds = c.ds;
+  d.inv_ds = 1.0f / c.ds;
+  d.S = p.S;
+  d.T = p.T;
+  d.n_obs = p.n_obs;
+  d.flags = p.flags;
+  d.n_path = c.n_path;
+  d.instance = p.instance;
+  const uint64_t seed = p.seed + seed_offset;
+  d.seed_lo = (uint32_t)(seed & 0xffffffffu);
+  d.seed_hi = (uint32_t)(seed >> 32);
+  d.S_pad = L.S_pad;
+  d.n_wchunk = L.n_wchunk;
+  d.n_rgroup = L.n_rgroup;
+  d.n_ritems = L.n_wchunk * L.n_rgroup;
+  d.x0_resident = (p.flags & BRMPPI_X0_RESIDENT) ? 1u : 0u;
+  d.path = c.path;
+  d.u_nom = c.unom;
+  d.u_star = reinterpret_cast<float*>(base + L.off_ustar);
+  d.J = reinterpret_cast<float*>(base + L.off_J);
+  d.gam = reinterpret_cast<float*>(base + L.off_gam);
+  d.wpart = reinterpret_cast<float4*>(base + L.off_wpart);
+  d.rpart = reinterpret_cast<float*>(base + L.off_rpart);
+  d.counter = reinterpret_cast<uint32_t*>(base + L.off_counter);
+  d.stats = reinterpret_cast<float*>(base + L.off_out);
+  d.u_new = d.stats + 4;
+  d.plant_x = c.plant;
+  for (uint32_t i = 0; i < p.n_obs; ++i) d.obs[i] = p.obs[i];
+}
+
+uint32_t rollout_block(brmppi_ctx* ctx, int bucket) {
+  if (ctx->forced.block) return ctx->forced.block;
+  return ctx->shape[bucket].block;
+}
+
+hipEvent_t take_event(brmppi_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// launch with optional timing (kind: 0 rollout, 1 weights, 2 reduce, 3 plant)
+template <typename F>
+int timed(brmppi_ctx* ctx, hipStream_t st, int kind, F&& launch) {
+  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0;
+  TimedLaunch tl{kind, nullptr, nullptr};
+  if (prof) {
+    tl.a = take_event(ctx);
+    tl.b = take_event(ctx);
+    if (tl.a) HIPCHK(hipEventRecord(tl.a, st));
+  }
+  HIPCHK(launch());
+  if (prof && tl.b) {
+    HIPCHK(hipEventRecord(tl.b, st));
+    ctx->pending_timing.push_back(tl);
+  }
+  return 0;
+}
+
+// after a stream sync: fold recorded kernel timings into the profile
+void collect_timing(brmppi_ctx* ctx) {
+  for (auto& t : ctx->pending_timing) {
+    float ms = 0.0f;
+    if (t.a && t.b && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      ctx->prof.ms[t.kind] += ms;
+      ctx->prof.n[t.kind] += 1.0;
+    }
+    if (t.a) ctx->ev_pool.push_back(t.a);
+    if (t.b) ctx->ev_pool.push_back(t.b);
+  }
+  ctx->pending_timing.clear();
+}
+
+// enqueue rollout + weights + reduce of one instance whose descriptor is at d_desc
+int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
+                   const ScratchLayout& L) {
+  const int bucket = bucket_for(p.n_obs, p.flags);
+  const uint32_t block = rollout_block(ctx, bucket);
+  const uint32_t grid = (p.S + block - 1) / block;
+  int rc = timed(ctx, st, 0, [&] { return launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, st); });
+  if (rc) return rc;
+  rc = timed(ctx, st, 1, [&] { return launch_weights(d_desc, nullptr, L.n_wchunk, nullptr, L.n_wchunk, st); });
+  if (rc) return rc;
+  const uint32_t nr = L.n_wchunk * L.n_rgroup;
+  return timed(ctx, st, 2, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
+}
+
+int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
+  if (ctx->scratch.bytes >= bytes) return 0;
+  ctx->arena.release(ctx->scratch);
+  ctx->scratch = ctx->arena.alloc(bytes);
+  if (!ctx->scratch.ptr) return fail(BRMPPI_ENOMEM, "solve scratch does not fit in the arena");
+  return 0;
+}
+
+// zero the reduce counter of a fresh scratch layout
+int zero_counter(hipStream_t st, char* base, const ScratchLayout& L) {
+  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(base + L.off_counter), 0u, 4, st));
+  return 0;
+}
+
+int upload_nominal(brmppi_ctx* ctx, hipStream_t st, Controller& c, const float* u, uint32_t T, char* pin) {
+  std::memcpy(pin, u, sizeof(float) * 3 * T);
+  HIPCHK(hipMemcpyAsync(c.unom, pin, sizeof(float) * 3 * T, hipMemcpyHostToDevice, st));
+  (void)ctx;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// plain solve
+// ---------------------------------------------------------------------------
+int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out, brmppi_stats* st) {
+  const auto t_start = Clock::now();
+  int rc = validate(ctx, p);
+  if (rc) return rc;
+  if (!out || !out->u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
+  Controller& c = ctx->ctrl[p->controller];
+  const ScratchLayout L = scratch_layout(p->S, p->T);
+  const size_t desc_off = L.bytes;
+  const size_t need = desc_off + round_up(sizeof(SolveDesc), 256);
+  const bool fresh = ctx->scratch.bytes < need;
+  if ((rc = ensure_scratch(ctx, need))) return rc;
+  char* base = ctx->scratch.ptr;
+  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + desc_off);
+  hipStream_t s = ctx->streams[0];
+  (void)fresh;
+  if ((rc = zero_counter(s, base, L))) return rc;
+
+  const size_t out_floats = 4 + 3 * (size_t)p->T;
+  const size_t pin_need = round_up(sizeof(SolveDesc), 256) + round_up(sizeof(float) * 3 * p->T, 256) +
+                          out_floats * sizeof(float);
+  if ((rc = ctx->pin.ensure(pin_need))) return rc;
+  char* pin = ctx->pin.ptr;
+  SolveDesc* h_desc = reinterpret_cast<SolveDesc*>(pin);
+  char* pin_u = pin + round_up(sizeof(SolveDesc), 256);
+  float* pin_out = reinterpret_cast<float*>(pin_u + round_up(sizeof(float) * 3 * p->T, 256));
+
+  fill_desc(*h_desc, *p, c, L, base, 0);
+  if (p->u_nom && (rc = upload_nominal(ctx, s, c, p->u_nom, p->T, pin_u))) return rc;
+  HIPCHK(hipMemcpyAsync(d_desc, h_desc, sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+  if ((rc = enqueue_single(ctx, s, d_desc, *p, L))) return rc;
+  HIPCHK(hipMemcpyAsync(pin_out, base + L.off_out, out_floats * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  collect_timing(ctx);
+  if (out->J_out) HIPCHK(hipMemcpy(out->J_out, base + L.off_J, sizeof(float) * p->S, hipMemcpyDeviceToHost));
+  if (out->useq_out) {
+    HIPCHK(hipMemcpy2D(out->useq_out, sizeof(float) * p->S, base + L.off_ustar, sizeof(float) * L.S_pad,
+                       sizeof(float) * p->S, 3 * (size_t)p->T, hipMemcpyDeviceToHost));
+  }
+  const int status = (int)pin_out[3];
+  std::memcpy(out->u_out, pin_out + 4, sizeof(float) * 3 * p->T);
+  if (status == BRMPPI_OK) c.warm_T = p->T;
+  else if (p->u_nom) c.warm_T = p->T;   // the uploaded sequence stays resident
+  if (st) {
+    st->J_min = pin_out[0];
+    st->Z = pin_out[1];
+    st->ess = pin_out[2];
+    st->status = status;
+    st->latency_us = std::chrono::duration<double, std::micro>(Clock::now() - t_start).count();
+  }
+  if (status != BRMPPI_OK) return fail(status, "every rollout cost was non-finite");
+  return BRMPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched solve: descriptor table + tile list + work lists, persistent kernels
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  std::vector<SolveDesc> descs;
+  std::vector<Tile> tiles;
+  std::vector<Item> witems, ritems;
+  std::vector<ScratchLayout> layouts;
+  std::vector<size_t> scratch_off;   // offset of each instance's scratch inside the block
+  size_t off_descs = 0, off_tiles = 0, off_witems = 0, off_ritems = 0, header_bytes = 0, total = 0;
+  int bucket = 0;
+  uint32_t block = 128;
+};
+
+void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, BatchPlan& bp) {
+  bp.layouts.resize(n);
+  bp.bucket = 0;
+  for (uint32_t i = 0; i < n; ++i) bp.bucket = std::max(bp.bucket, bucket_for(ps[i]->n_obs, ps[i]->flags));
+  // a batch mixing guided and unguided instances runs the guided kernel; the
+  // unguided instances take its GUIDANCE_OFF path inside the tile loop
+  bool any_off = false, any_on = false;
+  for (uint32_t i = 0; i < n; ++i) ((ps[i]->flags & BRMPPI_GUIDANCE_OFF) ? any_off : any_on) = true;
+  if (any_on && bp.bucket == 0) bp.bucket = 2;
+  (void)any_off;
+  bp.block = rollout_block(ctx, bp.bucket);
+  size_t n_tiles = 0, n_w = 0, n_r = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T);
+    n_tiles += (ps[i]->S + bp.block - 1) / bp.block;
+    n_w += bp.layouts[i].n_wchunk;
+    n_r += (size_t)bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup;
+  }
+  size_t o = 0;
+  bp.off_descs = o;
+  o = round_up(o + sizeof(SolveDesc) * n, 256);
+  bp.off_tiles = o;
+  o = round_up(o + sizeof(Tile) * n_tiles, 256);
+  bp.off_witems = o;
+  o = round_up(o + sizeof(Item) * n_w, 256);
+  bp.off_ritems = o;
+  o = round_up(o + sizeof(Item) * n_r, 256);
+  bp.header_bytes = o;
+  bp.scratch_off.resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    bp.scratch_off[i] = o;
+    o += bp.layouts[i].bytes;
+  }
+  bp.total = o;
+}
+
+void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, char* base, BatchPlan& bp) {
+  bp.descs.resize(n);
+  bp.tiles.clear();
+  bp.witems.clear();
+  bp.ritems.clear();
+  struct TC {
+    double cost;
+    Tile t;
+  };
+  std::vector<TC> tc;
+  for (uint32_t i = 0; i < n; ++i) {
+    const brmppi_problem& p = *ps[i];
+    fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0);
+    // guidance-off instances inside a guided batch: the flag is honoured per tile
+    const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + p.n_obs));
+    for (uint32_t s0 = 0; s0 < p.S; s0 += bp.block) tc.push_back({cost, Tile{i, s0}});
+    for (uint32_t c = 0; c < bp.layouts[i].n_wchunk; ++c) bp.witems.push_back(Item{i, c});
+    for (uint32_t k = 0; k < bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup; ++k) bp.ritems.push_back(Item{i, k});
+  }
+  // longest tiles first (stable: instance order breaks ties)
+  std::stable_sort(tc.begin(), tc.end(), [](const TC& a, const TC& b) { return a.cost > b.cost; });
+  bp.tiles.reserve(tc.size());
+  for (auto& x : tc) bp.tiles.push_back(x.t);
+}
+
+uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_tiles) {
+  const int per_cu = rollout_blocks_per_cu(bucket, block);
+  const size_t g = (size_t)ctx->n_cu * (size_t)std::max(per_cu, 1);
+  return (uint32_t)std::max<size_t>(1, std::min(g, n_tiles));
+}
+
+int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& bp, BatchCounters* ctr,
+                  bool timing) {
+  const SolveDesc* descs = reinterpret_cast<const SolveDesc*>(base + bp.off_descs);
+  const Tile* tiles = reinterpret_cast<const Tile*>(base + bp.off_tiles);
+  const Item* wi = reinterpret_cast<const Item*>(base + bp.off_witems);
+  const Item* ri = reinterpret_cast<const Item*>(base + bp.off_ritems);
+  const uint32_t nt = (uint32_t)bp.tiles.size(), nw = (uint32_t)bp.witems.size(), nr = (uint32_t)bp.ritems.size();
+  const uint32_t g_roll = persistent_grid(ctx, bp.bucket, bp.block, nt);
+  const uint32_t g_w = std::max<uint32_t>(1, std::min<uint32_t>(nw, (uint32_t)ctx->n_cu * 8));
+  const uint32_t g_r = std::max<uint32_t>(1, std::min<uint32_t>(nr, (uint32_t)ctx->n_cu * 8));
+  auto L0 = [&] { return launch_rollout(bp.bucket, descs, tiles, nt, ctr, g_roll, bp.block, st); };
+  auto L1 = [&] { return launch_weights(descs, wi, nw, ctr, g_w, st); };
+  auto L2 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
+  int rc;
+  if (timing) {
+    if ((rc = timed(ctx, st, 0, L0))) return rc;
+    if ((rc = timed(ctx, st, 1, L1))) return rc;
+    return timed(ctx, st, 2, L2);
+  }
+  HIPCHK(L0());
+  HIPCHK(L1());
+  HIPCHK(L2());
+  return 0;
+}
+
+// upload everything a batch needs from `pin` (header area) into `base`
+size_t stage_batch(const BatchPlan& bp, char* pin) {
+  std::memcpy(pin + bp.off_descs, bp.descs.data(), sizeof(SolveDesc) * bp.descs.size());
+  std::memcpy(pin + bp.off_tiles, bp.tiles.data(), sizeof(Tile) * bp.tiles.size());
+  std::memcpy(pin + bp.off_witems, bp.witems.data(), sizeof(Item) * bp.witems.size());
+  std::memcpy(pin + bp.off_ritems, bp.ritems.data(), sizeof(Item) * bp.ritems.size());
+  return bp.header_bytes;
+}
+
+void drop_graph(brmppi_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_key.clear();
+}
+
+int solve_batch_locked(brmppi_ctx* ctx, const brmppi_problem* probs, uint32_t n, float* const* u_outs,
+                       brmppi_stats* stats) {
+  const auto t_start = Clock::now();
+  if (!probs || !u_outs || n == 0 || n > BRMPPI_MAX_BATCH) return fail(BRMPPI_EINVAL, "bad batch arguments");
+  std::vector<const brmppi_problem*> ps(n);
+  std::vector<uint8_t> seen(ctx->ctrl.size(), 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    int rc = validate(ctx, &probs[i]);
+    if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+    if (!u_outs[i]) return fail(BRMPPI_EINVAL, "u_outs[i] is NULL");
+    if (seen[probs[i].controller]) return fail(BRMPPI_EINVAL, "a controller appears twice in one batch");
+    seen[probs[i].controller] = 1;
+    ps[i] = &probs[i];
+  }
+  BatchPlan bp;
+  plan_layout(ctx, ps.data(), n, bp);
+  int rc;
+  if ((rc = ensure_scratch(ctx, bp.total))) return rc;
+  char* base = ctx->scratch.ptr;
+  plan_fill(ctx, ps.data(), n, base, bp);
+  hipStream_t s = ctx->streams[0];
+  // staging: header, nominal sequences, outputs
+  size_t u_bytes = 0, out_floats = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (ps[i]->u_nom) u_bytes += round_up(sizeof(float) * 3 * ps[i]->T, 256);
+    out_floats += 4 + 3 * ps[i]->T;
+  }
+  if ((rc = ctx->pin.ensure(bp.header_bytes + u_bytes + out_floats * sizeof(float)))) return rc;
+  char* pin = ctx->pin.ptr;
+  stage_batch(bp, pin);
+  char* pu = pin + bp.header_bytes;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!ps[i]->u_nom) continue;
+    if ((rc = upload_nominal(ctx, s, ctx->ctrl[ps[i]->controller], ps[i]->u_nom, ps[i]->T, pu))) return rc;
+    pu += round_up(sizeof(float) * 3 * ps[i]->T, 256);
+  }
+  float* pout = reinterpret_cast<float*>(pu);
+  HIPCHK(hipMemcpyAsync(base, pin, bp.header_bytes, hipMemcpyHostToDevice, s));
+  for (uint32_t i = 0; i < n; ++i) {
+    if ((rc = zero_counter(s, base + bp.scratch_off[i], bp.layouts[i]))) return rc;
+  }
+  BatchCounters* ctr = ctx->counters;
+  // graph: keyed by everything that is baked into the captured launches
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(), bp.witems.size(), bp.ritems.size(),
+                               (uint64_t)bp.bucket, bp.block, (uint64_t)(uintptr_t)s, (uint64_t)n};
+  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0;
+  if (prof) {
+    if ((rc = enqueue_batch(ctx, s, base, bp, ctr, true))) return rc;
+  } else {
+    if (key != ctx->graph_key || !ctx->graph_exec) {
+      drop_graph(ctx);
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_batch(ctx, s, base, bp, ctr, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      ctx->graph = g;
+      HIPCHK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+      ctx->graph_key = key;
+    }
+    HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
+  }
+  // outputs: each instance's [stats | u_new] block
+  size_t of = 0;
+  std::vector<size_t> pos(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    pos[i] = of;
+    const size_t nf = 4 + 3 * ps[i]->T;
+    HIPCHK(hipMemcpyAsync(pout + of, base + bp.scratch_off[i] + bp.layouts[i].off_out, nf * sizeof(float),
+                          hipMemcpyDeviceToHost, s));
+    of += nf;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  collect_timing(ctx);
+  const double lat = std::chrono::duration<double, std::micro>(Clock::now() - t_start).count();
+  int worst = BRMPPI_OK;
+  for (uint32_t i = 0; i < n; ++i) {
+    const float* o = pout + pos[i];
+    const int status = (int)o[3];
+    std::memcpy(u_outs[i], o + 4, sizeof(float) * 3 * ps[i]->T);
+    Controller& c = ctx->ctrl[ps[i]->controller];
+    if (status == BRMPPI_OK || ps[i]->u_nom) c.warm_T = ps[i]->T;
+    if (stats) {
+      stats[i].J_min = o[0];
+      stats[i].Z = o[1];
+      stats[i].ess = o[2];
+      stats[i].status = status;
+      stats[i].latency_us = lat;
+    }
+    if (status != BRMPPI_OK) worst = status;
+  }
+  if (worst != BRMPPI_OK) return fail(worst, "an instance had only non-finite costs");
+  return BRMPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// closed loop on the device
+// ---------------------------------------------------------------------------
+int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up, double* x_out,
+                       float* u_applied) {
+  if (!p0 || n_up == 0) return fail(BRMPPI_EINVAL, "bad closed-loop arguments");
+  if (p0->controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  Controller& c = ctx->ctrl[p0->controller];
+  brmppi_problem p = *p0;
+  const bool resume = (p.flags & BRMPPI_X0_RESIDENT) != 0;
+  if (!resume) {
+    if (!c.plant) return fail(BRMPPI_ESTATE, "controller has no path (brmppi_set_path)");
+    for (int k = 0; k < 8; ++k)
+      if (!std::isfinite(p.x0[k])) return fail(BRMPPI_EINVAL, "non-finite x0");
+    c.plant_set = true;  // provisional, for validate(); restored below on error
+  }
+  p.flags |= BRMPPI_X0_RESIDENT;
+  int rc = validate(ctx, &p);
+  if (rc) {
+    if (!resume) c.plant_set = false;
+    return rc;
+  }
+  const ScratchLayout L = scratch_layout(p.S, p.T);
+  const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
+  const size_t log_off = L.bytes + desc_bytes * n_up;
+  const size_t need = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
+                      round_up(sizeof(float) * 3 * n_up, 256);
+  if ((rc = ensure_scratch(ctx, need))) return rc;
+  char* base = ctx->scratch.ptr;
+  hipStream_t s = ctx->streams[0];
+  const size_t pin_need = desc_bytes * n_up + round_up(sizeof(float) * 3 * p.T, 256) + 256 +
+                          sizeof(double) * 8 * (n_up + 1) + sizeof(float) * 3 * n_up;
+  if ((rc = ctx->pin.ensure(pin_need))) return rc;
+  char* pin = ctx->pin.ptr;
+  double* d_xlog = reinterpret_cast<double*>(base + log_off);
+  float* d_ulog = reinterpret_cast<float*>(base + log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256));
+  for (uint32_t k = 0; k < n_up; ++k) {
+    SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
+    fill_desc(*hd, p, c, L, base, k);
+  }
+  char* pin_u = pin + desc_bytes * n_up;
+  char* pin_x = pin_u + round_up(sizeof(float) * 3 * p.T, 256);
+  if (!resume) {
+    double* px = reinterpret_cast<double*>(pin_x);
+    for (int k = 0; k < 8; ++k) px[k] = (double)p0->x0[k];
+    HIPCHK(hipMemcpyAsync(c.plant, px, sizeof(double) * 8, hipMemcpyHostToDevice, s));
+  }
+  if (p.u_nom && (rc = upload_nominal(ctx, s, c, p.u_nom, p.T, pin_u))) return rc;
+  HIPCHK(hipMemcpyAsync(base + L.bytes, pin, desc_bytes * n_up, hipMemcpyHostToDevice, s));
+  if ((rc = zero_counter(s, base, L))) return rc;
+  HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+  for (uint32_t k = 0; k < n_up; ++k) {
+    const SolveDesc* dd = reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
+    if ((rc = enqueue_single(ctx, s, dd, p, L))) return rc;
+    if ((rc = timed(ctx, s, 3, [&] { return launch_plant(dd, s); }))) return rc;
+    if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+    if (u_applied)
+      HIPCHK(hipMemcpyAsync(d_ulog + 3 * k, base + L.off_out + 4 * sizeof(float), sizeof(float) * 3,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  double* hx = reinterpret_cast<double*>(pin_x + 256);
+  float* hu = reinterpret_cast<float*>(hx + 8 * (n_up + 1));
+  if (x_out) HIPCHK(hipMemcpyAsync(hx, d_xlog, sizeof(double) * 8 * (n_up + 1), hipMemcpyDeviceToHost, s));
+  if (u_applied) HIPCHK(hipMemcpyAsync(hu, d_ulog, sizeof(float) * 3 * n_up, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  collect_timing(ctx);
+  if (x_out) std::memcpy(x_out, hx, sizeof(double) * 8 * (n_up + 1));
+  if (u_applied) std::memcpy(u_applied, hu, sizeof(float) * 3 * n_up);
+  c.plant_set = true;
+  c.warm_T = p.T;
+  return BRMPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// served form
+// ---------------------------------------------------------------------------
+// device bytes one request adds to a served batch: scratch, descriptor, its
+// tiles (at the smallest block size) and work items, plus alignment slack
+size_t request_footprint(const brmppi_problem& p) {
+  const ScratchLayout L = scratch_layout(p.S, p.T);
+  const size_t tiles = (p.S + 63) / 64;
+  const size_t items = L.n_wchunk + (size_t)L.n_wchunk * L.n_rgroup;
+  return L.bytes + sizeof(SolveDesc) + (tiles + items) * 8 + 4 * 256;
+}
+
+// launch one batch of admitted requests on stream slot `slot` (ctx->mu held)
+int launch_served(brmppi_ctx* ctx, ServedBatch& b) {
+  const uint32_t n = (uint32_t)b.reqs.size();
+  std::vector<const brmppi_problem*> ps(n);
+  for (uint32_t i = 0; i < n; ++i) ps[i] = &b.reqs[i]->prob;
+  BatchPlan bp;
+  plan_layout(ctx, ps.data(), n, bp);
+  b.mem = ctx->arena.alloc(bp.total);
+  if (!b.mem.ptr) return fail(BRMPPI_ENOMEM, "served batch does not fit");
+  char* base = b.mem.ptr;
+  plan_fill(ctx, ps.data(), n, base, bp);
+  hipStream_t s = ctx->streams[b.slot];
+  size_t u_bytes = 0, out_floats = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (ps[i]->u_nom) u_bytes += round_up(sizeof(float) * 3 * ps[i]->T, 256);
+    out_floats += 4 + 3 * ps[i]->T;
+  }
+  int rc;
+  if ((rc = ctx->slot_pin[b.slot].ensure(bp.header_bytes + u_bytes + out_floats * sizeof(float)))) return rc;
+  char* pin = ctx->slot_pin[b.slot].ptr;
+  stage_batch(bp, pin);
+  char* pu = pin + bp.header_bytes;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!ps[i]->u_nom) continue;
+    if ((rc = upload_nominal(ctx, s, ctx->ctrl[ps[i]->controller], ps[i]->u_nom, ps[i]->T, pu))) return rc;
+    pu += round_up(sizeof(float) * 3 * ps[i]->T, 256);
+  }
+  float* pout = reinterpret_cast<float*>(pu);
+  HIPCHK(hipMemcpyAsync(base, pin, bp.header_bytes, hipMemcpyHostToDevice, s));
+  for (uint32_t i = 0; i < n; ++i)
+    if ((rc = zero_counter(s, base + bp.scratch_off[i], bp.layouts[i]))) return rc;
+  if ((rc = enqueue_batch(ctx, s, base, bp, ctx->counters + 1 + b.slot, false))) return rc;
+  b.out_pos.resize(n);
+  size_t of = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    b.out_pos[i] = of;
+    const size_t nf = 4 + 3 * ps[i]->T;
+    HIPCHK(hipMemcpyAsync(pout + of, base + bp.scratch_off[i] + bp.layouts[i].off_out, nf * sizeof(float),
+                          hipMemcpyDeviceToHost, s));
+    of += nf;
+  }
+  b.out_floats = of;
+  b.out_off = (size_t)(reinterpret_cast<char*>(pout) - pin);
+  if (!b.done_ev) HIPCHK(hipEventCreateWithFlags(&b.done_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(b.done_ev, s));
+  return 0;
+}
+
+void retire_served(brmppi_ctx* ctx, ServedBatch& b) {
+  const float* pout = reinterpret_cast<const float*>(ctx->slot_pin[b.slot].ptr + b.out_off);
+  const auto now = Clock::now();
+  for (size_t i = 0; i < b.reqs.size(); ++i) {
+    Request* r = b.reqs[i];
+    const float* o = pout + b.out_pos[i];
+    r->status = (int)o[3];
+    r->result.assign(o + 4, o + 4 + 3 * r->prob.T);
+    r->st.J_min = o[0];
+    r->st.Z = o[1];
+    r->st.ess = o[2];
+    r->st.status = r->status;
+    r->st.latency_us = std::chrono::duration<double, std::micro>(now - r->t_submit).count();
+    r->done = true;
+    Controller& c = ctx->ctrl[r->prob.controller];
+    c.busy = false;
+    if (r->status == BRMPPI_OK || r->prob.u_nom) c.warm_T = r->prob.T;
+  }
+  ctx->arena.release(b.mem);
+  ctx->slot_busy[b.slot] = false;
+}
+
+void fail_batch(brmppi_ctx* ctx, ServedBatch& b, int code) {
+  for (Request* r : b.reqs) {
+    r->status = code;
+    r->st.status = code;
+    r->done = true;
+    ctx->ctrl[r->prob.controller].busy = false;
+  }
+  ctx->arena.release(b.mem);
+  ctx->slot_busy[b.slot] = false;
+}
+
+void request_loop(brmppi_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  while (true) {
+    bool progressed = false;
+    // retire finished batches (in any order)
+    for (size_t i = 0; i < ctx->inflight.size();) {
+      hipError_t q = hipEventQuery(ctx->inflight[i].done_ev);
+      if (q == hipSuccess) {
+        retire_served(ctx, ctx->inflight[i]);
+        (void)hipEventDestroy(ctx->inflight[i].done_ev);
+        ctx->inflight.erase(ctx->inflight.begin() + i);
+        progressed = true;
+      } else if (q != hipErrorNotReady) {
+        fail_batch(ctx, ctx->inflight[i], BRMPPI_EDEVICE);
+        ctx->inflight.erase(ctx->inflight.begin() + i);
+        progressed = true;
+      } else {
+        ++i;
+      }
+    }
+    if (progressed) ctx->cv.notify_all();
+    // admit queued requests into a new batch on a free stream slot
+    int slot = -1;
+    for (uint32_t k = 0; k < ctx->n_streams; ++k)
+      if (!ctx->slot_busy[k]) {
+        slot = (int)k;
+        break;
+      }
+    if (slot >= 0 && !ctx->queue.empty()) {
+      ServedBatch b;
+      b.slot = slot;
+      size_t budget_bytes = 0;
+      std::vector<uint8_t> taken(ctx->ctrl.size(), 0);
+      for (auto it = ctx->queue.begin(); it != ctx->queue.end() && b.reqs.size() < BRMPPI_MAX_BATCH;) {
+        Request* r = *it;
+        Controller& c = ctx->ctrl[r->prob.controller];
+        // one request per controller per batch, in submission order
+        if (c.busy || taken[r->prob.controller]) {
+          taken[r->prob.controller] = 1;
+          ++it;
+          continue;
+        }
+        if (!r->prob.u_nom && c.warm_T != r->prob.T) {
+          // every earlier request of this controller has finished and none left
+          // a warm start of length T
+          r->status = BRMPPI_ESTATE;
+          r->st.status = BRMPPI_ESTATE;
+          r->done = true;
+          it = ctx->queue.erase(it);
+          progressed = true;
+          continue;
+        }
+        const size_t fp = request_footprint(r->prob);
+        if (!ctx->arena.fits(budget_bytes + fp)) {
+          taken[r->prob.controller] = 1;
+          ++it;
+          continue;
+        }
+        budget_bytes += fp;
+        taken[r->prob.controller] = 1;
+        b.reqs.push_back(r);
+        it = ctx->queue.erase(it);
+      }
+      if (progressed) ctx->cv.notify_all();
+      if (!b.reqs.empty()) {
+        for (Request* r : b.reqs) ctx->ctrl[r->prob.controller].busy = true;
+        ctx->slot_busy[slot] = true;
+        const int rc = launch_served(ctx, b);
+        if (rc != BRMPPI_OK) {
+          if (rc == BRMPPI_ENOMEM && b.mem.ptr == nullptr) {
+            // could not get the packed block: requeue at the front and retry later
+            for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) {
+              ctx->ctrl[(*it)->prob.controller].busy = false;
+              ctx->queue.push_front(*it);
+            }
+            ctx->slot_busy[slot] = false;
+          } else {
+            fail_batch(ctx, b, rc);
+            ctx->cv.notify_all();
+          }
+        } else {
+          ctx->inflight.push_back(std::move(b));
+        }
+        progressed = true;
+      }
+    }
+    if (!ctx->running && ctx->queue.empty() && ctx->inflight.empty()) break;
+    if (!progressed) {
+      if (ctx->inflight.empty() && ctx->queue.empty())
+        ctx->cv.wait_for(lk, std::chrono::milliseconds(5));
+      else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      }
+    }
+  }
+}
+
+int copy_problem(Request& r, const brmppi_problem* p) {
+  r.prob = *p;
+  r.params = *p->params;
+  r.prob.params = &r.params;
+  r.obs.assign(p->obs, p->obs + p->n_obs);
+  r.prob.obs = r.obs.empty() ? nullptr : r.obs.data();
+  if (p->u_nom) {
+    r.unom.assign(p->u_nom, p->u_nom + 3 * p->T);
+    r.prob.u_nom = r.unom.data();
+  }
+  return 0;
+}
+
+int load_tune(brmppi_ctx* ctx) {
+  if (ctx->tune_path.empty()) return 0;
+  std::ifstream f(ctx->tune_path);
+  if (!f) return 0;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  // format: {"bucket_<b>": <block>, ...}
+  for (int b : {0, 2, 8, 16, 32}) {
+    const std::string k = "\"bucket_" + std::to_string(b) + "\"";
+    const size_t at = s.find(k);
+    if (at == std::string::npos) continue;
+    const size_t colon = s.find(':', at);
+    if (colon == std::string::npos) continue;
+    const long v = std::strtol(s.c_str() + colon + 1, nullptr, 10);
+    if (v >= 64 && v <= kMaxBlock && v % 64 == 0) ctx->shape[b].block = (uint32_t)v;
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* brmppi_last_error(void) { return g_err.c_str(); }
+
+int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
+  if (!cfg || !out) return fail(BRMPPI_EINVAL, "null config or output pointer");
+  *out = nullptr;
+  if (!cfg->arena || (reinterpret_cast<uintptr_t>(cfg->arena) % 256) != 0)
+    return fail(BRMPPI_EINVAL, "arena must be a 256-byte aligned device pointer");
+  if (cfg->arena_bytes < (1u << 20)) return fail(BRMPPI_EINVAL, "arena smaller than 1 MiB");
+  if (cfg->n_streams < 1 || cfg->n_streams > 4) return fail(BRMPPI_EINVAL, "n_streams must be 1..4");
+  for (uint32_t k = 0; k < cfg->n_streams; ++k)
+    if (!cfg->streams[k]) return fail(BRMPPI_EINVAL, "stream handle is NULL");
+  if (cfg->max_controllers == 0 || cfg->max_controllers > 65536)
+    return fail(BRMPPI_EINVAL, "max_controllers must be 1..65536");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, cfg->arena) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(BRMPPI_EINVAL, "arena is not device memory");
+  }
+  HIPCHK(hipSetDevice(cfg->device));
+  std::unique_ptr<brmppi_ctx> ctx(new brmppi_ctx());
+  ctx->device = cfg->device;
+  ctx->arena.init(cfg->arena, cfg->arena_bytes);
+  ctx->n_streams = cfg->n_streams;
+  for (uint32_t k = 0; k < cfg->n_streams; ++k) ctx->streams[k] = static_cast<hipStream_t>(cfg->streams[k]);
+  ctx->max_inflight = cfg->max_inflight ? cfg->max_inflight : 4096;
+  ctx->flags = cfg->flags;
+  if (cfg->autotune_cache) ctx->tune_path = cfg->autotune_cache;
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cfg->device));
+  ctx->n_cu = ncu > 0 ? ncu : 256;
+  for (auto& s : ctx->shape) s.block = 128;
+  ctx->shape[0].block = 256;
+  ctx->ctrl.resize(cfg->max_controllers);
+  ctx->counters_blk = ctx->arena.alloc(sizeof(BatchCounters) * 5);
+  if (!ctx->counters_blk.ptr) return fail(BRMPPI_ENOMEM, "arena too small");
+  ctx->counters = reinterpret_cast<BatchCounters*>(ctx->counters_blk.ptr);
+  {
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->counters), 0u,
+                                   sizeof(BatchCounters) * 5 / 4, ctx->streams[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->streams[0]);
+    if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("counter init: ") + hipGetErrorString(e));
+  }
+  load_tune(ctx.get());
+  ctx->running = true;
+  brmppi_ctx* raw = ctx.release();
+  raw->loop = std::thread(request_loop, raw);
+  *out = raw;
+  return BRMPPI_OK;
+}
+
+int brmppi_destroy(brmppi_ctx* ctx) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->running = false;
+  }
+  ctx->cv.notify_all();
+  if (ctx->loop.joinable()) ctx->loop.join();
+  for (uint32_t k = 0; k < ctx->n_streams; ++k) (void)hipStreamSynchronize(ctx->streams[k]);
+  drop_graph(ctx);
+  collect_timing(ctx);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  ctx->pin.release();
+  for (auto& p : ctx->slot_pin) p.release();
+  delete ctx;
+  return BRMPPI_OK;
+}
+
+int brmppi_set_path(brmppi_ctx* ctx, uint32_t controller, const float* path, uint32_t n, float ds) {
+  if (!ctx || !path) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  if (n < 2 || n > BRMPPI_MAX_PATH) return fail(BRMPPI_EINVAL, "path needs 2..BRMPPI_MAX_PATH waypoints");
+  if (!(ds > 0) || !std::isfinite(ds)) return fail(BRMPPI_EINVAL, "ds must be positive");
+  for (size_t i = 0; i < (size_t)n * 4; ++i)
+    if (!std::isfinite(path[i])) return fail(BRMPPI_EINVAL, "non-finite path value");
+  Controller& c = ctx->ctrl[controller];
+  if (c.busy) return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  if (!c.mem.ptr) {
+    c.mem = ctx->arena.alloc(sizeof(float) * 3 * BRMPPI_MAX_T + 256 + sizeof(double) * 8);
+    if (!c.mem.ptr) return fail(BRMPPI_ENOMEM, "controller state does not fit in the arena");
+    c.unom = reinterpret_cast<float*>(c.mem.ptr);
+    c.plant = reinterpret_cast<double*>(c.mem.ptr + round_up(sizeof(float) * 3 * BRMPPI_MAX_T, 256));
+  }
+  if (c.path_blk.bytes < sizeof(float4) * n) {
+    Block nb = ctx->arena.alloc(sizeof(float4) * n);
+    if (!nb.ptr) return fail(BRMPPI_ENOMEM, "path does not fit in the arena");
+    ctx->arena.release(c.path_blk);
+    c.path_blk = nb;
+  }
+  c.path = reinterpret_cast<float4*>(c.path_blk.ptr);
+  HIPCHK(hipMemcpy(c.path, path, sizeof(float4) * n, hipMemcpyHostToDevice));
+  c.n_path = n;
+  c.ds = ds;
+  return BRMPPI_OK;
+}
+
+int brmppi_get_nominal(brmppi_ctx* ctx, uint32_t controller, float* u, uint32_t T) {
+  if (!ctx || !u) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  Controller& c = ctx->ctrl[controller];
+  if (!c.unom || c.warm_T == 0) return fail(BRMPPI_ESTATE, "no resident warm start");
+  if (T != c.warm_T) return fail(BRMPPI_EINVAL, "T differs from the resident warm start");
+  if (c.busy) return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  HIPCHK(hipStreamSynchronize(ctx->streams[0]));
+  HIPCHK(hipMemcpy(u, c.unom, sizeof(float) * 3 * T, hipMemcpyDeviceToHost));
+  return BRMPPI_OK;
+}
+
+int brmppi_set_nominal(brmppi_ctx* ctx, uint32_t controller, const float* u, uint32_t T) {
+  if (!ctx || !u) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  if (T < 1 || T > BRMPPI_MAX_T) return fail(BRMPPI_EINVAL, "T out of range");
+  Controller& c = ctx->ctrl[controller];
+  if (!c.unom) return fail(BRMPPI_ESTATE, "controller has no path (brmppi_set_path)");
+  if (c.busy) return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  for (size_t i = 0; i < (size_t)3 * T; ++i)
+    if (!std::isfinite(u[i])) return fail(BRMPPI_EINVAL, "non-finite nominal value");
+  HIPCHK(hipStreamSynchronize(ctx->streams[0]));
+  HIPCHK(hipMemcpy(c.unom, u, sizeof(float) * 3 * T, hipMemcpyHostToDevice));
+  c.warm_T = T;
+  return BRMPPI_OK;
+}
+
+int brmppi_set_state(brmppi_ctx* ctx, uint32_t controller, const double x[8]) {
+  if (!ctx || !x) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  Controller& c = ctx->ctrl[controller];
+  if (!c.plant) return fail(BRMPPI_ESTATE, "controller has no path (brmppi_set_path)");
+  for (int k = 0; k < 8; ++k)
+    if (!std::isfinite(x[k])) return fail(BRMPPI_EINVAL, "non-finite state");
+  HIPCHK(hipStreamSynchronize(ctx->streams[0]));
+  HIPCHK(hipMemcpy(c.plant, x, sizeof(double) * 8, hipMemcpyHostToDevice));
+  c.plant_set = true;
+  return BRMPPI_OK;
+}
+
+int brmppi_get_state(brmppi_ctx* ctx, uint32_t controller, double x[8]) {
+  if (!ctx || !x) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  Controller& c = ctx->ctrl[controller];
+  if (!c.plant || !c.plant_set) return fail(BRMPPI_ESTATE, "no resident plant state");
+  HIPCHK(hipStreamSynchronize(ctx->streams[0]));
+  HIPCHK(hipMemcpy(x, c.plant, sizeof(double) * 8, hipMemcpyDeviceToHost));
+  return BRMPPI_OK;
+}
+
+int brmppi_solve_ex(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out, brmppi_stats* st) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (p && p->controller < ctx->ctrl.size() && ctx->ctrl[p->controller].busy)
+    return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  return solve_locked(ctx, p, out, st);
+}
+
+int brmppi_solve(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st) {
+  brmppi_outputs o{u_out, nullptr, nullptr};
+  return brmppi_solve_ex(ctx, p, &o, st);
+}
+
+int brmppi_solve_batch(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n, float* const* u_outs,
+                       brmppi_stats* st) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (uint32_t i = 0; p && i < n; ++i)
+    if (p[i].controller < ctx->ctrl.size() && ctx->ctrl[p[i].controller].busy)
+      return fail(BRMPPI_EAGAIN, "a controller has a request in flight");
+  return solve_batch_locked(ctx, p, n, u_outs, st);
+}
+
+int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_updates, double* x_out,
+                       float* u_applied) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (p && p->controller < ctx->ctrl.size() && ctx->ctrl[p->controller].busy)
+    return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  return closed_loop_locked(ctx, p, n_updates, x_out, u_applied);
+}
+
+int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket) {
+  if (!ctx || !ticket) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (p && (p->flags & BRMPPI_X0_RESIDENT)) return fail(BRMPPI_EINVAL, "X0_RESIDENT is not served");
+  // a missing warm start is allowed when an earlier queued request of the same
+  // controller will leave one; the request thread re-checks at launch
+  int rc = BRMPPI_OK;
+  if (!p) return fail(BRMPPI_EINVAL, "null problem");
+  {
+    // validate everything except the warm-start length
+    brmppi_problem q = *p;
+    std::vector<float> dummy;
+    if (!q.u_nom && q.controller < ctx->ctrl.size() && q.T >= 1 && q.T <= BRMPPI_MAX_T) {
+      dummy.assign((size_t)3 * q.T, 0.0f);
+      q.u_nom = dummy.data();
+    }
+    rc = validate(ctx, &q);
+    if (rc) return rc;
+  }
+  const size_t fp = request_footprint(*p);
+  if (fp > ctx->arena.size()) return fail(BRMPPI_ENOMEM, "request can never fit in the arena");
+  if (ctx->n_active >= ctx->max_inflight) return fail(BRMPPI_EAGAIN, "max_inflight requests queued");
+  std::unique_ptr<Request> r(new Request());
+  r->ticket = ctx->next_ticket++;
+  copy_problem(*r, p);
+  r->t_submit = Clock::now();
+  Request* raw = r.get();
+  ctx->reqs[raw->ticket] = std::move(r);
+  ctx->queue.push_back(raw);
+  ctx->n_active++;
+  *ticket = raw->ticket;
+  ctx->cv.notify_all();
+  return BRMPPI_OK;
+}
+
+int brmppi_poll(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return fail(BRMPPI_ENOTICKET, "unknown or consumed ticket");
+  Request* r = it->second.get();
+  if (!r->done) return BRMPPI_PENDING;
+  if (!u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
+  const int status = r->status;
+  if (!r->result.empty()) std::memcpy(u_out, r->result.data(), sizeof(float) * r->result.size());
+  if (st) *st = r->st;
+  ctx->reqs.erase(it);
+  ctx->n_active--;
+  if (status != BRMPPI_OK) return fail(status, "request failed or had only non-finite costs");
+  return BRMPPI_OK;
+}
+
+int brmppi_wait(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st, uint32_t timeout_ms) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  const auto deadline = Clock::now() + std::chrono::milliseconds(timeout_ms);
+  while (true) {
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      auto it = ctx->reqs.find(ticket);
+      if (it == ctx->reqs.end()) return fail(BRMPPI_ENOTICKET, "unknown or consumed ticket");
+      if (!it->second->done) {
+        if (Clock::now() >= deadline) return fail(BRMPPI_ETIMEDOUT, "deadline passed");
+        ctx->cv.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+    }
+    return brmppi_poll(ctx, ticket, u_out, st);
+  }
+}
+
+int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t lanes) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (block == 0) {
+    ctx->forced = LaunchShape{0, 1};
+    return BRMPPI_OK;
+  }
+  if (block < 64 || block > (uint32_t)kMaxBlock || block % 64) return fail(BRMPPI_EINVAL, "block must be 64..256, multiple of 64");
+  if (lanes != 1) return fail(BRMPPI_EINVAL, "lanes per sample must be 1");
+  ctx->forced = LaunchShape{block, lanes};
+  drop_graph(ctx);
+  return BRMPPI_OK;
+}
+
+int brmppi_autotune(brmppi_ctx* ctx) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  // synthetic problem per bucket: straight path, obstacles around it
+  const uint32_t S = 8192, T = 32;
+  const uint32_t n_path = 400;
+  std::vector<float> path(4 * n_path);
+  for (uint32_t i = 0; i < n_path; ++i) {
+    path[4 * i] = 0.1f * i;
+    path[4 * i + 1] = 0.0f;
+    path[4 * i + 2] = 0.0f;
+    path[4 * i + 3] = 0.0f;
+  }
+  const ScratchLayout L = scratch_layout(S, T);
+  const size_t need = L.bytes + round_up(sizeof(SolveDesc), 256) + round_up(sizeof(float4) * n_path, 256) +
+                      round_up(sizeof(float) * 3 * T, 256) + 256;
+  int rc;
+  if ((rc = ensure_scratch(ctx, need))) return rc;
+  char* base = ctx->scratch.ptr;
+  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + L.bytes);
+  float4* d_path = reinterpret_cast<float4*>(base + L.bytes + round_up(sizeof(SolveDesc), 256));
+  float* d_unom = reinterpret_cast<float*>(reinterpret_cast<char*>(d_path) + round_up(sizeof(float4) * n_path, 256));
+  hipStream_t s = ctx->streams[0];
+  HIPCHK(hipMemcpy(d_path, path.data(), sizeof(float4) * n_path, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(d_unom, 0, sizeof(float) * 3 * T));
+  brmppi_params P{};
+  P.Ts = 0.05f; P.l1 = 4.0f; P.lh = 0.5f; P.l2 = 10.0f; P.dtheta_max = 0.7f; P.kappa = 0.05f; P.r_disc = 1.0f;
+  P.Qc = 2; P.Ql = 2; P.Qth1 = 1; P.Qth2 = 1; P.R_j = 0.05f; P.R_w = 0.05f; P.mu = 0.5f; P.nu_bar = 2;
+  P.W_j = 1; P.W_w = 11.1f; P.W_a = 25; P.rho = 0.1f; P.j_lo = -2; P.j_hi = 2; P.w_lo = -0.9f; P.w_hi = 0.9f;
+  P.alpha0 = 0.5f; P.alpha_lo = -1; P.alpha_hi = 1; P.sigma_j = 1; P.sigma_w = 0.3f; P.sigma_nu = 0.5f;
+  P.sigma_a = 0.2f; P.h_eps = 1e-5f;
+  std::string json = "{";
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int bucket : {0, 2, 8, 16, 32}) {
+    SolveDesc h{};
+    std::memset(&h, 0, sizeof(h));
+    h.prm = P;
+    h.lambda = 1.0f;
+    h.inv_lambda = 1.0f;
+    h.x0[2] = 1.0f;
+    h.ds = 0.1f;
+    h.inv_ds = 10.0f;
+    h.S = S;
+    h.T = T;
+    h.n_obs = bucket;
+    h.flags = bucket == 0 ? BRMPPI_GUIDANCE_OFF : 0u;
+    h.n_path = n_path;
+    h.S_pad = L.S_pad;
+    h.n_wchunk = L.n_wchunk;
+    h.n_rgroup = L.n_rgroup;
+    h.n_ritems = L.n_wchunk * L.n_rgroup;
+    h.path = d_path;
+    h.u_nom = d_unom;
+    h.u_star = reinterpret_cast<float*>(base + L.off_ustar);
+    h.J = reinterpret_cast<float*>(base + L.off_J);
+    for (int o = 0; o < bucket; ++o) {
+      h.obs[o].cx = 2.0f + 1.5f * o;
+      h.obs[o].cy = (o % 2) ? 2.5f : -2.5f;
+      h.obs[o].mx = 0.6f;
+      h.obs[o].my = 0.4f;
+      h.obs[o].heading = 0.3f * o;
+      h.obs[o].e = 2.0f;
+    }
+    HIPCHK(hipMemcpy(d_desc, &h, sizeof(h), hipMemcpyHostToDevice));
+    uint32_t best = ctx->shape[bucket].block;
+    float best_ms = 1e30f;
+    for (uint32_t block : {64u, 128u, 256u}) {
+      const uint32_t grid = (S + block - 1) / block;
+      HIPCHK(launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, s));
+      HIPCHK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) HIPCHK(launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, s));
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = block;
+      }
+    }
+    ctx->shape[bucket].block = best;
+    json += std::string(json.size() > 1 ? ", " : "") + "\"bucket_" + std::to_string(bucket) + "\": " + std::to_string(best);
+  }
+  json += "}\n";
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(ctx);
+  if (!ctx->tune_path.empty()) {
+    std::ofstream f(ctx->tune_path);
+    if (f) f << json;
+  }
+  return BRMPPI_OK;
+}
+
+int brmppi_profile_read(brmppi_ctx* ctx, double out[8]) {
+  if (!ctx || !out) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (int k = 0; k < 4; ++k) {
+    out[2 * k] = ctx->prof.ms[k];
+    out[2 * k + 1] = ctx->prof.n[k];
+  }
+  return BRMPPI_OK;
+}
+
+int brmppi_profile_reset(brmppi_ctx* ctx) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->prof = Profile{};
+  return BRMPPI_OK;
+}
+
+int brmppi_debug_philox(brmppi_ctx* ctx, const uint32_t* ctr, const uint32_t key[2], uint32_t n, uint32_t* out) {
+  if (!ctx || !ctr || !key || !out || n == 0 || n > (1u << 24)) return fail(BRMPPI_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Block b = ctx->arena.alloc(sizeof(uint32_t) * 8 * (size_t)n);
+  if (!b.ptr) return fail(BRMPPI_ENOMEM, "debug buffer does not fit");
+  uint32_t* d_in = reinterpret_cast<uint32_t*>(b.ptr);
+  uint32_t* d_out = d_in + 4 * (size_t)n;
+  hipStream_t s = ctx->streams[0];
+  int rc = BRMPPI_OK;
+  do {
+    hipError_t e = hipMemcpyAsync(d_in, ctr, sizeof(uint32_t) * 4 * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_philox_dump(d_in, key[0], key[1], n, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(uint32_t) * 4 * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(BRMPPI_EDEVICE, hipGetErrorString(e));
+  } while (0);
+  ctx->arena.release(b);
+  return rc;
+}
+
+int brmppi_debug_normals(brmppi_ctx* ctx, uint64_t seed, uint32_t instance, const uint32_t* s_tau, uint32_t n,
+                         uint32_t K, float* out) {
+  if (!ctx || !s_tau || !out || n == 0 || n > (1u << 22) || K == 0 || K > 64) return fail(BRMPPI_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Block b = ctx->arena.alloc(sizeof(uint32_t) * 2 * (size_t)n + 256 + sizeof(float) * (size_t)n * K);
+  if (!b.ptr) return fail(BRMPPI_ENOMEM, "debug buffer does not fit");
+  uint32_t* d_in = reinterpret_cast<uint32_t*>(b.ptr);
+  float* d_out = reinterpret_cast<float*>(b.ptr + round_up(sizeof(uint32_t) * 2 * (size_t)n, 256));
+  hipStream_t s = ctx->streams[0];
+  int rc = BRMPPI_OK;
+  do {
+    hipError_t e = hipMemcpyAsync(d_in, s_tau, sizeof(uint32_t) * 2 * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_normals_dump((uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), instance, d_in, n, K, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(float) * (size_t)n * K, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(BRMPPI_EDEVICE, hipGetErrorString(e));
+  } while (0);
+  ctx->arena.release(b);
+  return rc;
+}
+
+}  // extern "C"
