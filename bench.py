@@ -1,0 +1,346 @@
+#!/usr/bin/env python3
+"""Throughput of the BR-MPPI control update on one MI355X.
+
+Default workload (the reverse-parking closed loop): S = 8192 samples, horizon
+T = 50, Ts = 0.05 s, eight parked-vehicle ellipses, 200 receding-horizon
+updates.  A "step" is one control update: Philox noise + S rollouts with
+barrier-rate guidance and contouring cost + weights + weighted average +
+warm-start shift, followed by the FP64 plant step that closes the loop.  The
+whole loop is device-resident: the path, warm start, obstacles and plant state
+live in HBM and no host round trip happens between updates.
+
+  value = S * T * steps / wall time of the timed loop   [sample-steps/s]
+
+Printed as one JSON line; extra fields carry the plain-solve latency
+percentiles, the batched and served forms against plain per-instance solves,
+the paper's own problem shape, the roofline of the rollout kernel and the CPU
+oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (packed), AMD spec
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_05773_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_c2_traffic.json")
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work of the rollout kernel (counted from its source: add, sub,
+# mul = 1 flop, fma = 2, each transcendental / reciprocal / division = 1;
+# FP64 accumulations included; Philox integer ops excluded)
+# ---------------------------------------------------------------------------
+def flops_per_sample_step(n_obs: int, hitch: bool = True, guided: bool = True) -> int:
+    if not guided:
+        return 6 + 11 + 59 + 18 + 24          # inputs, trig, cost, dynamics, one noise block
+    nb = (5 + n_obs + 3) // 4                  # Philox blocks per step
+    base = 6 + 11 + 20 + 59 + 18               # inputs, trig, 2x2 solve, cost, dynamics
+    return base + 24 * nb + (120 if hitch else 0) + 125 * n_obs
+
+
+def rollout_flops(S: int, T: int, n_obs: int, hitch=True, guided=True) -> float:
+    return float(S) * (T * flops_per_sample_step(n_obs, hitch, guided) + 48)
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per rollout launch from the committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def note(msg):
+    """progress line on stderr (the JSON result is the only stdout line)"""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="control updates in the timed loop")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-solves", type=int, default=300)
+    ap.add_argument("--served-seconds", type=float, default=0.3, help="simulated seconds of the served leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true", help="only the timed closed loop")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs the control update on one MI355X; this build has no multi-GPU path "
+              "(one GPU per box). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.calib_copy:
+        n = 256 << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n, "launches": 5}))
+        return
+
+    from paper_2508_05773_amd import brmppi as B
+    from paper_2508_05773_amd import workloads as W
+
+    prob = W.config2()
+    S, T, n_obs = prob.S, prob.T, prob.n_obs
+    ctx = B.Context(arena_bytes=3 << 30, n_streams=2, max_controllers=600,
+                    profile=False, flags_extra=B.CTX_PROFILE_ROLLOUT)
+    h = ctx.h
+    ctx.set_path(0, prob.path, prob.ds)
+    pb = B.ProblemBuffers(prob, controller=0)
+
+    # ---- warm-up, then the timed closed loop from the start state ----
+    if args.warmup > 0:
+        B.brmppi_closed_loop(h, pb, args.warmup, want_x=False, want_u=False)
+    B.brmppi_profile_reset(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.brmppi_closed_loop(h, pb, args.steps, want_x=False, want_u=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = B.brmppi_profile_read(h)
+    x_end = B.brmppi_get_state(h, 0)
+    value = S * T * args.steps / wall
+    roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
+    flops = rollout_flops(S, T, n_obs)
+    achieved = flops / (roll_ms * 1e-3) / 1e12
+    traffic = load_traffic()
+    out = {
+        "metric": "sample-steps/s; MPPI solves/s + p50/p99 solve latency, batched vs plain",
+        "value": value,
+        "unit": "sample-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "reverse parking closed loop: S=8192, T=50, Ts=0.05 s, 8 parked-vehicle "
+                               "ellipses, 200 receding-horizon updates, device-resident",
+                   "S": S, "T": T, "n_obs": n_obs, "updates": args.steps},
+        "solves_per_s": args.steps / wall,
+        "final_state_finite": bool(np.all(np.isfinite(x_end))),
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+            "kernel": "k_rollout<8,true>", "flops_per_launch": flops, "avg_launch_ms": roll_ms,
+            "launches": prof["rollout"]["count"], "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "flops_per_sample_step": flops_per_sample_step(n_obs),
+        },
+    }
+
+    if not args.no_extras:
+        out.update(extras(args, B, W, ctx, prob))
+    ctx.close()
+
+    if not args.no_cpu:
+        note("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(W, prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def extras(args, B, W, ctx, prob):
+    import torch
+
+    h = ctx.h
+    res = {}
+    note("closed loop done; plain-solve latency")
+    # ---- plain blocking solve latency (host in, host out) ----
+    ctx.set_path(1, prob.path, prob.ds)
+    lat = []
+    for k in range(args.latency_solves + 10):
+        pbk = B.ProblemBuffers(prob, controller=1, with_nominal=(k == 0), seed=prob.seed + k)
+        _, st, _ = B.brmppi_solve(h, pbk)
+        if k >= 10:
+            lat.append(st["latency_us"] * 1e-3)
+    res["p50_ms"] = pct(lat, 50)
+    res["p99_ms"] = pct(lat, 99)
+    res["plain_solves_per_s"] = 1e3 / float(np.mean(lat))
+    res["pcie_inclusive_sample_steps_per_s"] = prob.S * prob.T * res["plain_solves_per_s"]
+
+    note("batched vs plain")
+    # ---- batched (one persistent launch in a HIP graph) vs plain per-instance ----
+    insts = W.config3()
+    for i, p in enumerate(insts):
+        ctx.set_path(100 + i, p.path, p.ds)
+    pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(insts)]
+    for pbi in pbs:
+        B.brmppi_solve(h, pbi)
+    torch.cuda.synchronize()
+    reps_p = 3
+    t0 = time.perf_counter()
+    for _ in range(reps_p):
+        for pbi in pbs:
+            B.brmppi_solve(h, pbi)
+    t_plain = (time.perf_counter() - t0) / reps_p
+    for _ in range(2):
+        B.brmppi_solve_batch(h, pbs)
+    reps_b = 10
+    t0 = time.perf_counter()
+    for _ in range(reps_b):
+        B.brmppi_solve_batch(h, pbs)
+    t_batch = (time.perf_counter() - t0) / reps_b
+    ss = sum(p.S * p.T for p in insts)
+    res["batched"] = {
+        "workload": "64 uneven instances: S in {1024..16384}, T in [20, 80], 0-16 obstacles",
+        "instances": len(insts), "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
+        "plain_solves_per_s": len(insts) / t_plain, "batched_solves_per_s": len(insts) / t_batch,
+        "speedup": t_plain / t_batch, "batched_sample_steps_per_s": ss / t_batch,
+    }
+
+    note("served")
+    # ---- served: continuous batching of 256 controllers vs sequential plain ----
+    res["served"] = served_leg(args, B, W, ctx)
+
+    note("paper shape")
+    # ---- the paper's own problem shape: H = 120, 5000 rollouts, 8 obstacles ----
+    pp = W.config2().copy(S=5000, T=120, params=W.make_params(0.04), u_nom=np.zeros((120, 3), np.float32))
+    ctx.set_path(2, pp.path, pp.ds)
+    lat = []
+    for k in range(40):
+        _, st, _ = B.brmppi_solve(h, B.ProblemBuffers(pp, controller=2, with_nominal=(k == 0), seed=k))
+        if k >= 5:
+            lat.append(st["latency_us"] * 1e-3)
+    res["paper_shape"] = {"S": 5000, "T": 120, "n_obs": 8, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                          "paper_ms": 9.9, "paper_hw": "unnamed single GPU, JAX"}
+    return res
+
+
+def served_leg(args, B, W, ctx):
+    h = ctx.h
+    ctrls = W.config4_controllers()
+    n = len(ctrls)
+    base_id = 300
+    pbs = []
+    for c, p in enumerate(ctrls):
+        ctx.set_path(base_id + c, p.path, p.ds)
+        B.brmppi_set_state(h, base_id + c, p.x0.astype(np.float64))
+        flags = B.X0_RESIDENT | B.ADVANCE_PLANT
+        pbs.append([B.ProblemBuffers(p, controller=base_id + c, with_nominal=True, flags=flags),
+                    B.ProblemBuffers(p, controller=base_id + c, with_nominal=False, flags=flags)])
+    events = W.config4_arrivals(n, args.served_seconds)
+    started = [False] * n
+    outstanding = []          # (ticket, T)
+    lat, done = [], 0
+    t_start = time.perf_counter()
+    ss_total = 0
+
+    def drain(block=False):
+        nonlocal done, ss_total
+        while outstanding:
+            t, T, ssk = outstanding[0]
+            if block:
+                u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
+            else:
+                u, st, rc = B.brmppi_poll(h, t, T, allow=(B.OK, B.PENDING, B.ENONFINITE))
+                if rc == B.PENDING:
+                    return
+            outstanding.pop(0)
+            lat.append(st["latency_us"] * 1e-3)
+            done += 1
+            ss_total += ssk
+
+    def outstanding_wait_one():
+        nonlocal done, ss_total
+        t, T, ssk = outstanding.pop(0)
+        u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
+        lat.append(st["latency_us"] * 1e-3)
+        done += 1
+        ss_total += ssk
+
+    for (te, c, k) in events:
+        while time.perf_counter() - t_start < te:
+            drain()
+        pb = pbs[c][1 if started[c] else 0]
+        pb.c.seed = (4000 + c * 100003 + k) & (2**64 - 1)
+        while True:
+            t, rc = B.brmppi_submit(h, pb, allow=(B.OK, B.EAGAIN))
+            if rc == B.OK:
+                break
+            # back-pressure: the queue is full, wait for the oldest request
+            outstanding_wait_one()
+        started[c] = True
+        outstanding.append((t, pb.c.T, pb.c.S * pb.c.T))
+        drain()
+    drain(block=True)
+    wall = time.perf_counter() - t_start
+    # sequential plain solves of the same kind of requests (first 512 events)
+    seq_events = events[:512]
+    t0 = time.perf_counter()
+    for (te, c, k) in seq_events:
+        B.brmppi_solve(h, pbs[c][1], allow=(B.OK, B.ENONFINITE))
+    t_seq = time.perf_counter() - t0
+    return {
+        "workload": "256 controllers, S in {2048, 8192, 32768}, T in {30, 50, 100}, 0-32 obstacles "
+                    "(10 % moving), one request per 10 ms tick + Exp(1 ms) jitter, closed loop on the device",
+        "simulated_s": args.served_seconds, "requests": len(events), "wall_s": wall,
+        "solves_per_s": done / wall, "sample_steps_per_s": ss_total / wall,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "sequential_plain_solves_per_s": len(seq_events) / t_seq,
+        "speedup_vs_sequential": (done / wall) / (len(seq_events) / t_seq),
+    }
+
+
+def cpu_baseline(W, prob, seconds):
+    """The FP64 oracle on the host cores, on a bounded sample of the same update."""
+    from oracle import oracle as O
+
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count() or 1
+    threads = max(1, min(16, cpus))
+    sub = prob.copy(S=1024)
+    O.solve(sub.copy(S=64), nthreads=threads)          # build + warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.solve(sub.copy(seed=sub.seed + reps), nthreads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    v = sub.S * sub.T * reps / el
+    return {"value": v, "unit": "sample-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} updates of the reverse-parking problem with S=1024 of its 8192 samples "
+                      f"(T=50, 8 obstacles) in {el:.1f} s on {threads} threads"}
+
+
+if __name__ == "__main__":
+    main()

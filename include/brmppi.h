@@ -62,9 +62,13 @@ extern "C" {
 #define BRMPPI_HITCH_OFF 2u       /* no hitch-angle rows (N_c = n_obs) */
 #define BRMPPI_X0_RESIDENT 4u     /* start from the controller's device-resident plant
                                      state (brmppi_set_state / brmppi_closed_loop) */
+#define BRMPPI_ADVANCE_PLANT 8u   /* after the update, advance the resident plant state by
+                                     the first averaged input (jerk and steer rate clamped
+                                     to [j_lo, j_hi], [w_lo, w_hi]) with eq. (6) in FP64 */
 
 /* ---- context flags ------------------------------------------------------ */
-#define BRMPPI_CTX_PROFILE 1u     /* time every kernel with HIP events */
+#define BRMPPI_CTX_PROFILE 1u     /* time every kernel of the blocking calls with HIP events */
+#define BRMPPI_CTX_PROFILE_ROLLOUT 2u /* time only the rollout kernel (lower overhead) */
 
 typedef struct brmppi_ctx brmppi_ctx;
 
@@ -121,7 +125,8 @@ typedef struct {
   float lambda;               /* temperature of the weights, > 0 */
   uint64_t seed;              /* Philox key */
   uint32_t instance;          /* Philox counter word 3 */
-  uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT */
+  uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT |
+                                 BRMPPI_ADVANCE_PLANT */
   const brmppi_params* params;/* required */
 } brmppi_problem;
 
@@ -182,7 +187,9 @@ int brmppi_solve_batch(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n, flo
 /* Queue one update; returns at once with a ticket.  The request thread admits
  * queued requests as controller slots and arena memory free up and launches
  * them together with whatever else is pending, overlapping on the device.
- * Requests of one controller run in submission order.
+ * Requests of one controller run in submission order; with
+ * BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT a controller runs its closed loop
+ * on the device (each request starts where the previous one left the plant).
  * Errors: EINVAL, ESTATE, EAGAIN (max_inflight reached), ENOMEM (can never fit). */
 int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket);
 /* Non-blocking: BRMPPI_PENDING while in flight; otherwise copies the result

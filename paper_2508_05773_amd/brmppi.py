@@ -20,8 +20,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "brmppi.h")
 # return codes / flags (include/brmppi.h)
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EAGAIN, ENONFINITE, ENOTICKET, EDEVICE, ETIMEDOUT, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
-GUIDANCE_OFF, HITCH_OFF, X0_RESIDENT = 1, 2, 4
-CTX_PROFILE = 1
+GUIDANCE_OFF, HITCH_OFF, X0_RESIDENT, ADVANCE_PLANT = 1, 2, 4, 8
+CTX_PROFILE, CTX_PROFILE_ROLLOUT = 1, 2
 MAX_OBS, MAX_T = 32, 512
 
 PARAM_FIELDS = (
@@ -321,7 +321,7 @@ class Context:
     """Owns a torch device arena and streams and the library context over them."""
 
     def __init__(self, arena_bytes=1 << 30, n_streams=2, max_controllers=512, profile=False,
-                 autotune_cache=None, max_inflight=0, device=0):
+                 autotune_cache=None, max_inflight=0, device=0, flags_extra=0):
         import torch
 
         if not torch.cuda.is_available():
@@ -340,7 +340,7 @@ class Context:
         cfg.max_inflight = max_inflight
         self._tc = autotune_cache.encode() if autotune_cache else None
         cfg.autotune_cache = self._tc
-        cfg.flags = CTX_PROFILE if profile else 0
+        cfg.flags = (CTX_PROFILE if profile else 0) | int(flags_extra)
         cfg.device = device
         torch.cuda.synchronize()
         self.h = brmppi_create(cfg)

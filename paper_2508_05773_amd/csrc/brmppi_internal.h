@@ -27,7 +27,8 @@ struct alignas(16) SolveDesc {
   uint32_t S_pad, n_wchunk, n_rgroup, n_ritems;
   uint32_t x0_resident, pad0, pad1, pad2;
   const float4* path;           // controller path (absolute coordinates)
-  float* u_nom;                 // 3T warm start (read by the rollout, shifted by the reduce)
+  const float* u_nom_in;        // 3T nominal sequence read by the rollout
+  float* u_nom_out;             // 3T warm-start slot of the controller (shift target)
   float* u_star;                // [3T][S_pad] applied inputs
   float* J;                     // [S_pad]
   float* gam;                   // [S_pad] exp(-(J - m_chunk)/lambda)
@@ -56,6 +57,7 @@ hipError_t launch_weights(const SolveDesc* descs, const Item* items, uint32_t n_
 hipError_t launch_reduce(const SolveDesc* descs, const Item* items, uint32_t n_items,
                          BatchCounters* ctr, uint32_t grid, hipStream_t stream);
 hipError_t launch_plant(const SolveDesc* desc, hipStream_t stream);
+hipError_t launch_plant_batch(const SolveDesc* descs, uint32_t n, hipStream_t stream);
 hipError_t launch_philox_dump(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t n, uint32_t* out,
                               hipStream_t stream);
 hipError_t launch_normals_dump(uint32_t seed_lo, uint32_t seed_hi, uint32_t instance, const uint32_t* s_tau,

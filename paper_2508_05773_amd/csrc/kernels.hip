@@ -174,7 +174,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
   double J = 0.0;
   const uint32_t S_pad = d.S_pad;
   float* __restrict__ ustar = d.u_star;
-  const float* __restrict__ unom = d.u_nom;
+  const float* __restrict__ unom = d.u_nom_in;
 
   for (uint32_t tau = 0; tau < d.T; ++tau) {
     // --- noise (Philox counter (s, tau, block, instance), key = seed) ---
@@ -559,12 +559,12 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_m
       const float U = acc * iZ;
       d.u_new[r] = U;
       // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
-      if (r >= 3) d.u_nom[r - 3] = U;
-      if (r + 3 >= R) d.u_nom[r] = U;
+      if (r >= 3) d.u_nom_out[r - 3] = U;
+      if (r + 3 >= R) d.u_nom_out[r] = U;
     }
   } else {
     // every cost non-finite: return the nominal sequence, keep the warm start
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) d.u_new[r] = d.u_nom[r];
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) d.u_new[r] = d.u_nom_in[r];
   }
   if (threadIdx.x == 0) {
     d.stats[0] = m;
@@ -649,9 +649,7 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
 // ---------------------------------------------------------------------------
 // Closed-loop plant: x <- Euler(x, clamp(U_new[0])) in FP64 (eq. (6))
 // ---------------------------------------------------------------------------
-__global__ void k_plant(const SolveDesc* __restrict__ dp) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const SolveDesc& d = *dp;
+__device__ void plant_step(const SolveDesc& d) {
   const brmppi_params& P = d.prm;
   double x[8];
   for (int k = 0; k < 8; ++k) x[k] = d.plant_x[k];
@@ -670,6 +668,18 @@ __global__ void k_plant(const SolveDesc* __restrict__ dp) {
   xn[6] = dl + Ts * w;
   xn[7] = x[7] + Ts * nu;
   for (int k = 0; k < 8; ++k) d.plant_x[k] = xn[k];
+}
+
+__global__ void k_plant(const SolveDesc* __restrict__ dp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  plant_step(*dp);
+}
+
+// batched: one thread per instance, only those that asked for it
+__global__ void k_plant_batch(const SolveDesc* __restrict__ descs, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (descs[i].flags & BRMPPI_ADVANCE_PLANT) plant_step(descs[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,6 +769,12 @@ hipError_t launch_reduce(const SolveDesc* descs, const Item* items, uint32_t n_i
 
 hipError_t launch_plant(const SolveDesc* desc, hipStream_t stream) {
   hipLaunchKernelGGL(k_plant, dim3(1), dim3(64), 0, stream, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_plant_batch(const SolveDesc* descs, uint32_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plant_batch, dim3((n + 63) / 64), dim3(64), 0, stream, descs, n);
   return hipGetLastError();
 }
 

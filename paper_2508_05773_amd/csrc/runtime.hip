@@ -142,11 +142,26 @@ struct Controller {
   bool busy = false;          // a served request is in flight
 };
 
-// layout of one instance's scratch inside a block
+// layout of one instance's scratch inside a block (off_out: [stats(4) | u_new(3T)]
+// for the plain and closed-loop paths; batches pack their outputs elsewhere)
 struct ScratchLayout {
-  size_t off_ustar, off_J, off_gam, off_wpart, off_rpart, off_counter, off_out, bytes;
+  size_t off_ustar, off_J, off_gam, off_wpart, off_rpart, off_out, bytes;
   uint32_t S_pad, n_wchunk, n_rgroup;
 };
+
+// one instance's uploaded inputs: [descriptor | reduce counter (zero) | nominal
+// sequence]; a single host-to-device copy carries all three
+struct InputBlock {
+  size_t counter, unom, bytes;
+};
+
+InputBlock input_block(uint32_t T, bool with_unom) {
+  InputBlock b;
+  b.counter = (sizeof(SolveDesc) + 255) / 256 * 256;
+  b.unom = b.counter + 256;
+  b.bytes = b.unom + (with_unom ? sizeof(float) * 3 * T : 0);
+  return b;
+}
 
 ScratchLayout scratch_layout(uint32_t S, uint32_t T) {
   ScratchLayout L;
@@ -164,9 +179,7 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T) {
   o = round_up(o + (size_t)L.n_wchunk * sizeof(float4), 256);
   L.off_rpart = o;
   o = round_up(o + (size_t)L.n_wchunk * 3 * T * sizeof(float), 256);
-  L.off_counter = o;
-  o = round_up(o + 16, 256);
-  L.off_out = o;  // stats[4] + u_new[3T]
+  L.off_out = o;
   o = round_up(o + (size_t)(4 + 3 * T) * sizeof(float), 256);
   L.bytes = o;
   return L;
@@ -274,8 +287,10 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (p->n_obs > BRMPPI_MAX_OBS) return fail(BRMPPI_EINVAL, "too many obstacles");
   if (p->n_obs > 0 && !p->obs) return fail(BRMPPI_EINVAL, "obstacles pointer is NULL");
   if (!p->params) return fail(BRMPPI_EINVAL, "params pointer is NULL");
-  if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT))
+  if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT))
     return fail(BRMPPI_EINVAL, "unknown flags");
+  if ((p->flags & BRMPPI_ADVANCE_PLANT) && !(p->flags & BRMPPI_X0_RESIDENT))
+    return fail(BRMPPI_EINVAL, "BRMPPI_ADVANCE_PLANT needs BRMPPI_X0_RESIDENT");
   const brmppi_params& P = *p->params;
   if (!finite_params(P)) return fail(BRMPPI_EINVAL, "non-finite parameter");
   if (!(P.Ts > 0) || !(P.l1 > 0) || !(P.l2 > 0) || !(P.h_eps > 0))
@@ -303,8 +318,10 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   return BRMPPI_OK;
 }
 
+// base: the instance's scratch; unom_dev: device copy of p.u_nom when the
+// caller supplied one; counter: a zeroed u32; out: [stats(4) | u_new(3T)]
 void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const ScratchLayout& L, char* base,
-               uint32_t seed_offset) {
+               uint32_t seed_offset, const float* unom_dev, uint32_t* counter, float* out) {
   std::memset(&d, 0, sizeof(d));
   d.prm = *p.params;
   d.lambda = p.lambda;
@@ -328,15 +345,16 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.n_ritems = L.n_wchunk * L.n_rgroup;
   d.x0_resident = (p.flags & BRMPPI_X0_RESIDENT) ? 1u : 0u;
   d.path = c.path;
-  d.u_nom = c.unom;
+  d.u_nom_in = (p.u_nom && unom_dev) ? unom_dev : c.unom;
+  d.u_nom_out = c.unom;
   d.u_star = reinterpret_cast<float*>(base + L.off_ustar);
   d.J = reinterpret_cast<float*>(base + L.off_J);
   d.gam = reinterpret_cast<float*>(base + L.off_gam);
   d.wpart = reinterpret_cast<float4*>(base + L.off_wpart);
   d.rpart = reinterpret_cast<float*>(base + L.off_rpart);
-  d.counter = reinterpret_cast<uint32_t*>(base + L.off_counter);
-  d.stats = reinterpret_cast<float*>(base + L.off_out);
-  d.u_new = d.stats + 4;
+  d.counter = counter;
+  d.stats = out;
+  d.u_new = out + 4;
   d.plant_x = c.plant;
   for (uint32_t i = 0; i < p.n_obs; ++i) d.obs[i] = p.obs[i];
 }
@@ -360,7 +378,8 @@ hipEvent_t take_event(brmppi_ctx* ctx) {
 // launch with optional timing (kind: 0 rollout, 1 weights, 2 reduce, 3 plant)
 template <typename F>
 int timed(brmppi_ctx* ctx, hipStream_t st, int kind, F&& launch) {
-  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0;
+  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0 ||
+                    ((ctx->flags & BRMPPI_CTX_PROFILE_ROLLOUT) != 0 && kind == 0);
   TimedLaunch tl{kind, nullptr, nullptr};
   if (prof) {
     tl.a = take_event(ctx);
@@ -400,7 +419,9 @@ int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, con
   rc = timed(ctx, st, 1, [&] { return launch_weights(d_desc, nullptr, L.n_wchunk, nullptr, L.n_wchunk, st); });
   if (rc) return rc;
   const uint32_t nr = L.n_wchunk * L.n_rgroup;
-  return timed(ctx, st, 2, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
+  rc = timed(ctx, st, 2, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
+  if (rc || !(p.flags & BRMPPI_ADVANCE_PLANT)) return rc;
+  return timed(ctx, st, 3, [&] { return launch_plant(d_desc, st); });
 }
 
 int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
@@ -408,19 +429,6 @@ int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
   ctx->arena.release(ctx->scratch);
   ctx->scratch = ctx->arena.alloc(bytes);
   if (!ctx->scratch.ptr) return fail(BRMPPI_ENOMEM, "solve scratch does not fit in the arena");
-  return 0;
-}
-
-// zero the reduce counter of a fresh scratch layout
-int zero_counter(hipStream_t st, char* base, const ScratchLayout& L) {
-  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(base + L.off_counter), 0u, 4, st));
-  return 0;
-}
-
-int upload_nominal(brmppi_ctx* ctx, hipStream_t st, Controller& c, const float* u, uint32_t T, char* pin) {
-  std::memcpy(pin, u, sizeof(float) * 3 * T);
-  HIPCHK(hipMemcpyAsync(c.unom, pin, sizeof(float) * 3 * T, hipMemcpyHostToDevice, st));
-  (void)ctx;
   return 0;
 }
 
@@ -434,28 +442,26 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   if (!out || !out->u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
   Controller& c = ctx->ctrl[p->controller];
   const ScratchLayout L = scratch_layout(p->S, p->T);
-  const size_t desc_off = L.bytes;
-  const size_t need = desc_off + round_up(sizeof(SolveDesc), 256);
-  const bool fresh = ctx->scratch.bytes < need;
-  if ((rc = ensure_scratch(ctx, need))) return rc;
+  // device: [scratch | input block]
+  const InputBlock IB = input_block(p->T, p->u_nom != nullptr);
+  const size_t in_off = L.bytes;
+  if ((rc = ensure_scratch(ctx, in_off + round_up(IB.bytes, 256)))) return rc;
   char* base = ctx->scratch.ptr;
-  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + desc_off);
+  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + in_off);
   hipStream_t s = ctx->streams[0];
-  (void)fresh;
-  if ((rc = zero_counter(s, base, L))) return rc;
 
   const size_t out_floats = 4 + 3 * (size_t)p->T;
-  const size_t pin_need = round_up(sizeof(SolveDesc), 256) + round_up(sizeof(float) * 3 * p->T, 256) +
-                          out_floats * sizeof(float);
+  const size_t pin_need = round_up(IB.bytes, 256) + out_floats * sizeof(float);
   if ((rc = ctx->pin.ensure(pin_need))) return rc;
   char* pin = ctx->pin.ptr;
   SolveDesc* h_desc = reinterpret_cast<SolveDesc*>(pin);
-  char* pin_u = pin + round_up(sizeof(SolveDesc), 256);
-  float* pin_out = reinterpret_cast<float*>(pin_u + round_up(sizeof(float) * 3 * p->T, 256));
+  float* pin_out = reinterpret_cast<float*>(pin + round_up(IB.bytes, 256));
 
-  fill_desc(*h_desc, *p, c, L, base, 0);
-  if (p->u_nom && (rc = upload_nominal(ctx, s, c, p->u_nom, p->T, pin_u))) return rc;
-  HIPCHK(hipMemcpyAsync(d_desc, h_desc, sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+  fill_desc(*h_desc, *p, c, L, base, 0, reinterpret_cast<const float*>(base + in_off + IB.unom),
+            reinterpret_cast<uint32_t*>(base + in_off + IB.counter), reinterpret_cast<float*>(base + L.off_out));
+  std::memset(pin + IB.counter, 0, IB.unom - IB.counter);
+  if (p->u_nom) std::memcpy(pin + IB.unom, p->u_nom, sizeof(float) * 3 * p->T);
+  HIPCHK(hipMemcpyAsync(d_desc, h_desc, IB.bytes, hipMemcpyHostToDevice, s));
   if ((rc = enqueue_single(ctx, s, d_desc, *p, L))) return rc;
   HIPCHK(hipMemcpyAsync(pin_out, base + L.off_out, out_floats * sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -467,8 +473,7 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   }
   const int status = (int)pin_out[3];
   std::memcpy(out->u_out, pin_out + 4, sizeof(float) * 3 * p->T);
-  if (status == BRMPPI_OK) c.warm_T = p->T;
-  else if (p->u_nom) c.warm_T = p->T;   // the uploaded sequence stays resident
+  if (status == BRMPPI_OK) c.warm_T = p->T;   // the shifted result is resident
   if (st) {
     st->J_min = pin_out[0];
     st->Z = pin_out[1];
@@ -489,7 +494,12 @@ struct BatchPlan {
   std::vector<Item> witems, ritems;
   std::vector<ScratchLayout> layouts;
   std::vector<size_t> scratch_off;   // offset of each instance's scratch inside the block
-  size_t off_descs = 0, off_tiles = 0, off_witems = 0, off_ritems = 0, header_bytes = 0, total = 0;
+  std::vector<size_t> unom_off;      // offset of each caller nominal sequence (header), or 0
+  std::vector<size_t> out_pos;       // float offset of each [stats(4) | u_new(3T)] in the outputs
+  // block layout: header [descs | tiles | witems | ritems | nominals | counters]
+  // (one upload), outputs (one download), then every instance's scratch
+  size_t off_descs = 0, off_tiles = 0, off_witems = 0, off_ritems = 0, off_counters = 0, header_bytes = 0;
+  size_t off_outs = 0, out_floats = 0, total = 0;
   int bucket = 0;
   uint32_t block = 128;
 };
@@ -521,7 +531,25 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
   o = round_up(o + sizeof(Item) * n_w, 256);
   bp.off_ritems = o;
   o = round_up(o + sizeof(Item) * n_r, 256);
+  // caller-supplied nominal sequences travel with the header
+  bp.unom_off.assign(n, 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!ps[i]->u_nom) continue;
+    bp.unom_off[i] = o;
+    o = round_up(o + sizeof(float) * 3 * ps[i]->T, 256);
+  }
+  bp.off_counters = o;                        // uploaded as zeros
+  o = round_up(o + sizeof(uint32_t) * n, 256);
   bp.header_bytes = o;
+  bp.off_outs = o;
+  bp.out_pos.resize(n);
+  size_t nf = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    bp.out_pos[i] = nf;
+    nf += 4 + 3 * (size_t)ps[i]->T;
+  }
+  bp.out_floats = nf;
+  o = round_up(o + sizeof(float) * nf, 256);
   bp.scratch_off.resize(n);
   for (uint32_t i = 0; i < n; ++i) {
     bp.scratch_off[i] = o;
@@ -542,7 +570,11 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
   std::vector<TC> tc;
   for (uint32_t i = 0; i < n; ++i) {
     const brmppi_problem& p = *ps[i];
-    fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0);
+    const float* unom_dev = p.u_nom ? reinterpret_cast<const float*>(base + bp.unom_off[i]) : nullptr;
+    uint32_t* counter = reinterpret_cast<uint32_t*>(base + bp.off_counters) + i;
+    float* out = reinterpret_cast<float*>(base + bp.off_outs) + bp.out_pos[i];
+    fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0, unom_dev,
+              counter, out);
     // guidance-off instances inside a guided batch: the flag is honoured per tile
     const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + p.n_obs));
     for (uint32_t s0 = 0; s0 < p.S; s0 += bp.block) tc.push_back({cost, Tile{i, s0}});
@@ -574,26 +606,39 @@ int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& 
   auto L0 = [&] { return launch_rollout(bp.bucket, descs, tiles, nt, ctr, g_roll, bp.block, st); };
   auto L1 = [&] { return launch_weights(descs, wi, nw, ctr, g_w, st); };
   auto L2 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
+  bool plant = false;
+  for (const SolveDesc& d : bp.descs) plant = plant || (d.flags & BRMPPI_ADVANCE_PLANT);
+  const uint32_t n_inst = (uint32_t)bp.descs.size();
   int rc;
   if (timing) {
     if ((rc = timed(ctx, st, 0, L0))) return rc;
     if ((rc = timed(ctx, st, 1, L1))) return rc;
-    return timed(ctx, st, 2, L2);
+    if ((rc = timed(ctx, st, 2, L2))) return rc;
+    if (plant) return timed(ctx, st, 3, [&] { return launch_plant_batch(descs, n_inst, st); });
+    return 0;
   }
   HIPCHK(L0());
   HIPCHK(L1());
   HIPCHK(L2());
+  if (plant) HIPCHK(launch_plant_batch(descs, n_inst, st));
   return 0;
 }
 
-// upload everything a batch needs from `pin` (header area) into `base`
-size_t stage_batch(const BatchPlan& bp, char* pin) {
+// write the header of a batch into pinned memory (uploaded to `base` in one copy)
+void stage_batch(const BatchPlan& bp, const brmppi_problem* const* ps, char* pin) {
   std::memcpy(pin + bp.off_descs, bp.descs.data(), sizeof(SolveDesc) * bp.descs.size());
   std::memcpy(pin + bp.off_tiles, bp.tiles.data(), sizeof(Tile) * bp.tiles.size());
   std::memcpy(pin + bp.off_witems, bp.witems.data(), sizeof(Item) * bp.witems.size());
   std::memcpy(pin + bp.off_ritems, bp.ritems.data(), sizeof(Item) * bp.ritems.size());
-  return bp.header_bytes;
+  for (size_t i = 0; i < bp.descs.size(); ++i)
+    if (ps[i]->u_nom) std::memcpy(pin + bp.unom_off[i], ps[i]->u_nom, sizeof(float) * 3 * ps[i]->T);
+  std::memset(pin + bp.off_counters, 0, bp.header_bytes - bp.off_counters);
 }
+
+// enqueue upload, kernels (or a graph of them) and the single download of a batch
+// whose block starts at `base`; `pin` holds header_bytes + out_floats floats
+int run_batch(brmppi_ctx* ctx, hipStream_t s, char* base, const BatchPlan& bp, BatchCounters* ctr, char* pin,
+              bool use_graph);
 
 void drop_graph(brmppi_ctx* ctx) {
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -601,6 +646,39 @@ void drop_graph(brmppi_ctx* ctx) {
   ctx->graph_exec = nullptr;
   ctx->graph = nullptr;
   ctx->graph_key.clear();
+}
+
+int run_batch(brmppi_ctx* ctx, hipStream_t s, char* base, const BatchPlan& bp, BatchCounters* ctr, char* pin,
+              bool use_graph) {
+  HIPCHK(hipMemcpyAsync(base, pin, bp.header_bytes, hipMemcpyHostToDevice, s));
+  int rc;
+  if (!use_graph) {
+    if ((rc = enqueue_batch(ctx, s, base, bp, ctr, true))) return rc;
+  } else {
+    // the captured launches bake in every pointer and count: key on them
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(), bp.witems.size(),
+                                       bp.ritems.size(), (uint64_t)bp.bucket, bp.block,
+                                       (uint64_t)(uintptr_t)s, bp.descs.size(), (uint64_t)(uintptr_t)ctr};
+    if (key != ctx->graph_key || !ctx->graph_exec) {
+      drop_graph(ctx);
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_batch(ctx, s, base, bp, ctr, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      ctx->graph = g;
+      HIPCHK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+      ctx->graph_key = key;
+    }
+    HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
+  }
+  HIPCHK(hipMemcpyAsync(pin + bp.header_bytes, base + bp.off_outs, bp.out_floats * sizeof(float),
+                        hipMemcpyDeviceToHost, s));
+  return 0;
 }
 
 int solve_batch_locked(brmppi_ctx* ctx, const brmppi_problem* probs, uint32_t n, float* const* u_outs,
@@ -624,71 +702,22 @@ int solve_batch_locked(brmppi_ctx* ctx, const brmppi_problem* probs, uint32_t n,
   char* base = ctx->scratch.ptr;
   plan_fill(ctx, ps.data(), n, base, bp);
   hipStream_t s = ctx->streams[0];
-  // staging: header, nominal sequences, outputs
-  size_t u_bytes = 0, out_floats = 0;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (ps[i]->u_nom) u_bytes += round_up(sizeof(float) * 3 * ps[i]->T, 256);
-    out_floats += 4 + 3 * ps[i]->T;
-  }
-  if ((rc = ctx->pin.ensure(bp.header_bytes + u_bytes + out_floats * sizeof(float)))) return rc;
+  if ((rc = ctx->pin.ensure(bp.header_bytes + bp.out_floats * sizeof(float)))) return rc;
   char* pin = ctx->pin.ptr;
-  stage_batch(bp, pin);
-  char* pu = pin + bp.header_bytes;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (!ps[i]->u_nom) continue;
-    if ((rc = upload_nominal(ctx, s, ctx->ctrl[ps[i]->controller], ps[i]->u_nom, ps[i]->T, pu))) return rc;
-    pu += round_up(sizeof(float) * 3 * ps[i]->T, 256);
-  }
-  float* pout = reinterpret_cast<float*>(pu);
-  HIPCHK(hipMemcpyAsync(base, pin, bp.header_bytes, hipMemcpyHostToDevice, s));
-  for (uint32_t i = 0; i < n; ++i) {
-    if ((rc = zero_counter(s, base + bp.scratch_off[i], bp.layouts[i]))) return rc;
-  }
-  BatchCounters* ctr = ctx->counters;
-  // graph: keyed by everything that is baked into the captured launches
-  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(), bp.witems.size(), bp.ritems.size(),
-                               (uint64_t)bp.bucket, bp.block, (uint64_t)(uintptr_t)s, (uint64_t)n};
-  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0;
-  if (prof) {
-    if ((rc = enqueue_batch(ctx, s, base, bp, ctr, true))) return rc;
-  } else {
-    if (key != ctx->graph_key || !ctx->graph_exec) {
-      drop_graph(ctx);
-      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_batch(ctx, s, base, bp, ctr, false);
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(s, &g);
-      if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-      }
-      if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-      ctx->graph = g;
-      HIPCHK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
-      ctx->graph_key = key;
-    }
-    HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
-  }
-  // outputs: each instance's [stats | u_new] block
-  size_t of = 0;
-  std::vector<size_t> pos(n);
-  for (uint32_t i = 0; i < n; ++i) {
-    pos[i] = of;
-    const size_t nf = 4 + 3 * ps[i]->T;
-    HIPCHK(hipMemcpyAsync(pout + of, base + bp.scratch_off[i] + bp.layouts[i].off_out, nf * sizeof(float),
-                          hipMemcpyDeviceToHost, s));
-    of += nf;
-  }
+  stage_batch(bp, ps.data(), pin);
+  const bool prof = (ctx->flags & (BRMPPI_CTX_PROFILE | BRMPPI_CTX_PROFILE_ROLLOUT)) != 0;
+  if ((rc = run_batch(ctx, s, base, bp, ctx->counters, pin, !prof))) return rc;
   HIPCHK(hipStreamSynchronize(s));
   collect_timing(ctx);
+  const float* pout = reinterpret_cast<const float*>(pin + bp.header_bytes);
   const double lat = std::chrono::duration<double, std::micro>(Clock::now() - t_start).count();
   int worst = BRMPPI_OK;
   for (uint32_t i = 0; i < n; ++i) {
-    const float* o = pout + pos[i];
+    const float* o = pout + bp.out_pos[i];
     const int status = (int)o[3];
     std::memcpy(u_outs[i], o + 4, sizeof(float) * 3 * ps[i]->T);
     Controller& c = ctx->ctrl[ps[i]->controller];
-    if (status == BRMPPI_OK || ps[i]->u_nom) c.warm_T = ps[i]->T;
+    if (status == BRMPPI_OK) c.warm_T = ps[i]->T;
     if (stats) {
       stats[i].J_min = o[0];
       stats[i].Z = o[1];
@@ -718,45 +747,53 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
       if (!std::isfinite(p.x0[k])) return fail(BRMPPI_EINVAL, "non-finite x0");
     c.plant_set = true;  // provisional, for validate(); restored below on error
   }
-  p.flags |= BRMPPI_X0_RESIDENT;
+  p.flags |= BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT;
   int rc = validate(ctx, &p);
   if (rc) {
     if (!resume) c.plant_set = false;
     return rc;
   }
   const ScratchLayout L = scratch_layout(p.S, p.T);
+  // device: [scratch | descriptors of every update | counter | nominal | logs];
+  // descriptors, counter and nominal sequence travel in one upload
   const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
-  const size_t log_off = L.bytes + desc_bytes * n_up;
+  const size_t in_off = L.bytes;
+  const size_t ctr_rel = desc_bytes * n_up;
+  const size_t unom_rel = ctr_rel + 256;
+  const size_t in_bytes = unom_rel + (p.u_nom ? sizeof(float) * 3 * p.T : 0);
+  const size_t log_off = in_off + round_up(in_bytes, 256);
   const size_t need = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
                       round_up(sizeof(float) * 3 * n_up, 256);
   if ((rc = ensure_scratch(ctx, need))) return rc;
   char* base = ctx->scratch.ptr;
   hipStream_t s = ctx->streams[0];
-  const size_t pin_need = desc_bytes * n_up + round_up(sizeof(float) * 3 * p.T, 256) + 256 +
-                          sizeof(double) * 8 * (n_up + 1) + sizeof(float) * 3 * n_up;
+  const size_t pin_need = round_up(in_bytes, 256) + 256 + sizeof(double) * 8 * (n_up + 1) +
+                          sizeof(float) * 3 * n_up;
   if ((rc = ctx->pin.ensure(pin_need))) return rc;
   char* pin = ctx->pin.ptr;
   double* d_xlog = reinterpret_cast<double*>(base + log_off);
   float* d_ulog = reinterpret_cast<float*>(base + log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256));
+  uint32_t* d_ctr = reinterpret_cast<uint32_t*>(base + in_off + ctr_rel);
+  const float* d_unom = reinterpret_cast<const float*>(base + in_off + unom_rel);
+  float* d_out = reinterpret_cast<float*>(base + L.off_out);
   for (uint32_t k = 0; k < n_up; ++k) {
     SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
-    fill_desc(*hd, p, c, L, base, k);
+    // only the first update reads the caller's sequence; later ones the shifted result
+    fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out);
   }
-  char* pin_u = pin + desc_bytes * n_up;
-  char* pin_x = pin_u + round_up(sizeof(float) * 3 * p.T, 256);
+  std::memset(pin + ctr_rel, 0, 256);
+  if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, sizeof(float) * 3 * p.T);
+  char* pin_x = pin + round_up(in_bytes, 256);
   if (!resume) {
     double* px = reinterpret_cast<double*>(pin_x);
     for (int k = 0; k < 8; ++k) px[k] = (double)p0->x0[k];
     HIPCHK(hipMemcpyAsync(c.plant, px, sizeof(double) * 8, hipMemcpyHostToDevice, s));
   }
-  if (p.u_nom && (rc = upload_nominal(ctx, s, c, p.u_nom, p.T, pin_u))) return rc;
-  HIPCHK(hipMemcpyAsync(base + L.bytes, pin, desc_bytes * n_up, hipMemcpyHostToDevice, s));
-  if ((rc = zero_counter(s, base, L))) return rc;
-  HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + in_off, pin, in_bytes, hipMemcpyHostToDevice, s));
+  if (x_out) HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
   for (uint32_t k = 0; k < n_up; ++k) {
     const SolveDesc* dd = reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
-    if ((rc = enqueue_single(ctx, s, dd, p, L))) return rc;
-    if ((rc = timed(ctx, s, 3, [&] { return launch_plant(dd, s); }))) return rc;
+    if ((rc = enqueue_single(ctx, s, dd, p, L))) return rc;   // includes the plant step
     if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
     if (u_applied)
       HIPCHK(hipMemcpyAsync(d_ulog + 3 * k, base + L.off_out + 4 * sizeof(float), sizeof(float) * 3,
@@ -784,7 +821,7 @@ size_t request_footprint(const brmppi_problem& p) {
   const ScratchLayout L = scratch_layout(p.S, p.T);
   const size_t tiles = (p.S + 63) / 64;
   const size_t items = L.n_wchunk + (size_t)L.n_wchunk * L.n_rgroup;
-  return L.bytes + sizeof(SolveDesc) + (tiles + items) * 8 + 4 * 256;
+  return L.bytes + sizeof(SolveDesc) + (tiles + items) * 8 + sizeof(float) * (4 + 6 * (size_t)p.T) + 8 * 256;
 }
 
 // launch one batch of admitted requests on stream slot `slot` (ctx->mu held)
@@ -799,37 +836,17 @@ int launch_served(brmppi_ctx* ctx, ServedBatch& b) {
   char* base = b.mem.ptr;
   plan_fill(ctx, ps.data(), n, base, bp);
   hipStream_t s = ctx->streams[b.slot];
-  size_t u_bytes = 0, out_floats = 0;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (ps[i]->u_nom) u_bytes += round_up(sizeof(float) * 3 * ps[i]->T, 256);
-    out_floats += 4 + 3 * ps[i]->T;
-  }
   int rc;
-  if ((rc = ctx->slot_pin[b.slot].ensure(bp.header_bytes + u_bytes + out_floats * sizeof(float)))) return rc;
+  if ((rc = ctx->slot_pin[b.slot].ensure(bp.header_bytes + bp.out_floats * sizeof(float)))) return rc;
   char* pin = ctx->slot_pin[b.slot].ptr;
-  stage_batch(bp, pin);
-  char* pu = pin + bp.header_bytes;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (!ps[i]->u_nom) continue;
-    if ((rc = upload_nominal(ctx, s, ctx->ctrl[ps[i]->controller], ps[i]->u_nom, ps[i]->T, pu))) return rc;
-    pu += round_up(sizeof(float) * 3 * ps[i]->T, 256);
-  }
-  float* pout = reinterpret_cast<float*>(pu);
+  stage_batch(bp, ps.data(), pin);
   HIPCHK(hipMemcpyAsync(base, pin, bp.header_bytes, hipMemcpyHostToDevice, s));
-  for (uint32_t i = 0; i < n; ++i)
-    if ((rc = zero_counter(s, base + bp.scratch_off[i], bp.layouts[i]))) return rc;
   if ((rc = enqueue_batch(ctx, s, base, bp, ctx->counters + 1 + b.slot, false))) return rc;
-  b.out_pos.resize(n);
-  size_t of = 0;
-  for (uint32_t i = 0; i < n; ++i) {
-    b.out_pos[i] = of;
-    const size_t nf = 4 + 3 * ps[i]->T;
-    HIPCHK(hipMemcpyAsync(pout + of, base + bp.scratch_off[i] + bp.layouts[i].off_out, nf * sizeof(float),
-                          hipMemcpyDeviceToHost, s));
-    of += nf;
-  }
-  b.out_floats = of;
-  b.out_off = (size_t)(reinterpret_cast<char*>(pout) - pin);
+  HIPCHK(hipMemcpyAsync(pin + bp.header_bytes, base + bp.off_outs, bp.out_floats * sizeof(float),
+                        hipMemcpyDeviceToHost, s));
+  b.out_pos = bp.out_pos;
+  b.out_floats = bp.out_floats;
+  b.out_off = bp.header_bytes;
   if (!b.done_ev) HIPCHK(hipEventCreateWithFlags(&b.done_ev, hipEventDisableTiming));
   HIPCHK(hipEventRecord(b.done_ev, s));
   return 0;
@@ -851,7 +868,7 @@ void retire_served(brmppi_ctx* ctx, ServedBatch& b) {
     r->done = true;
     Controller& c = ctx->ctrl[r->prob.controller];
     c.busy = false;
-    if (r->status == BRMPPI_OK || r->prob.u_nom) c.warm_T = r->prob.T;
+    if (r->status == BRMPPI_OK) c.warm_T = r->prob.T;
   }
   ctx->arena.release(b.mem);
   ctx->slot_busy[b.slot] = false;
@@ -1194,7 +1211,6 @@ int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_upda
 int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket) {
   if (!ctx || !ticket) return fail(BRMPPI_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (p && (p->flags & BRMPPI_X0_RESIDENT)) return fail(BRMPPI_EINVAL, "X0_RESIDENT is not served");
   // a missing warm start is allowed when an earlier queued request of the same
   // controller will leave one; the request thread re-checks at launch
   int rc = BRMPPI_OK;
@@ -1329,7 +1345,8 @@ int brmppi_autotune(brmppi_ctx* ctx) {
     h.n_rgroup = L.n_rgroup;
     h.n_ritems = L.n_wchunk * L.n_rgroup;
     h.path = d_path;
-    h.u_nom = d_unom;
+    h.u_nom_in = d_unom;
+    h.u_nom_out = d_unom;
     h.u_star = reinterpret_cast<float*>(base + L.off_ustar);
     h.J = reinterpret_cast<float*>(base + L.off_J);
     for (int o = 0; o < bucket; ++o) {

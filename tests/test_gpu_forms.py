@@ -1,0 +1,195 @@
+"""GPU tests of the batched, served and closed-loop forms.
+
+- batched (persistent kernels in a HIP graph) == plain per-instance solves,
+  bitwise, on uneven instances; every graph replay == the eager launch;
+- served: a request's result is bitwise the same alone and inside a mix of
+  concurrent requests; per-controller ordering and warm starts hold;
+- closed loop on the device: the first update equals a plain solve, and the
+  FP64 plant step matches the oracle's plant.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2508_05773_amd import brmppi as B
+from paper_2508_05773_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(arena_bytes=3 << 30, n_streams=3, max_controllers=700)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c3_small():
+    insts = W.config3(n_instances=24, seed=33)
+    # keep the test quick: cap the sample counts
+    return [p.copy(S=min(p.S, 4096)) for p in insts]
+
+
+def test_batched_equals_plain(ctx, c3_small):
+    log(f"  batched vs plain on {len(c3_small)} instances")
+    plain = []
+    for i, p in enumerate(c3_small):
+        ctx.set_path(100 + i, p.path, p.ds)
+        u, st, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=100 + i))
+        plain.append(u)
+    pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(c3_small)]
+    for rep in range(3):          # first call captures the graph, the rest replay it
+        outs, stats, _ = B.brmppi_solve_batch(ctx.h, pbs)
+        for i in range(len(c3_small)):
+            assert np.array_equal(outs[i], plain[i]), (rep, i)
+        # eager work between replays
+        B.brmppi_solve(ctx.h, B.ProblemBuffers(c3_small[0], controller=100))
+
+
+def test_batched_matches_oracle(ctx, c3_small):
+    from oracle import oracle as O
+    pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(c3_small)]
+    for i, p in enumerate(c3_small):
+        ctx.set_path(100 + i, p.path, p.ds)
+    outs, stats, _ = B.brmppi_solve_batch(ctx.h, pbs)
+    for i in (0, 5, 11, 23):
+        p = c3_small[i]
+        o = O.solve(p, nthreads=16)
+        tol = 1e-4 * np.array([4.0, 1.8, p.params["nu_bar"]])
+        du = np.abs(outs[i] - o["U_new"]).max(axis=0)
+        log(f"  batched inst {i}: S={p.S} T={p.T} n_obs={p.n_obs} U err {du}")
+        assert np.all(du <= tol)
+        assert stats[i]["J_min"] == pytest.approx(o["stats"]["J_min"], rel=1e-4)
+
+
+def test_batched_mixed_guidance_and_hitch(ctx):
+    """one launch holding guided, unguided and hitch-off instances"""
+    probs = [W.random_small(60 + k, S=500 + 37 * k, T=9 + k, n_obs=k % 5) for k in range(6)]
+    probs[1] = probs[1].copy(flags=W.FLAG_GUIDANCE_OFF)
+    probs[4] = probs[4].copy(flags=W.FLAG_HITCH_OFF)
+    for k, p in enumerate(probs):
+        ctx.set_path(200 + k, p.path, p.ds)
+    plain = [B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=200 + k))[0] for k, p in enumerate(probs)]
+    outs, _, _ = B.brmppi_solve_batch(ctx.h, [B.ProblemBuffers(p, controller=200 + k) for k, p in enumerate(probs)])
+    for k in range(len(probs)):
+        assert np.array_equal(outs[k], plain[k]), k
+
+
+def test_served_alone_vs_mix(ctx):
+    probs = W.config4_controllers(n_ctrl=40, seed=44)
+    probs = [p.copy(S=min(p.S, 8192), T=min(p.T, 50)) for p in probs]
+    for k, p in enumerate(probs):
+        ctx.set_path(300 + k, p.path, p.ds)
+    # alone: one request at a time
+    alone = []
+    for k, p in enumerate(probs[:8]):
+        t, _ = B.brmppi_submit(ctx.h, B.ProblemBuffers(p, controller=300 + k))
+        u, st, rc = B.brmppi_wait(ctx.h, t, p.T)
+        alone.append(u)
+    # in the mix: all 40 submitted at once (the first 8 again, same inputs)
+    tickets = []
+    for k, p in enumerate(probs):
+        t, _ = B.brmppi_submit(ctx.h, B.ProblemBuffers(p, controller=300 + k))
+        tickets.append(t)
+    mixed = [B.brmppi_wait(ctx.h, t, p.T)[0] for t, p in zip(tickets, probs)]
+    for k in range(8):
+        assert np.array_equal(alone[k], mixed[k]), k
+    # and the served result equals the plain solve
+    for k in (0, 3, 17, 39):
+        u, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(probs[k], controller=300 + k))
+        assert np.array_equal(u, mixed[k]), k
+
+
+def test_served_order_and_warm_start(ctx):
+    """two requests of one controller: the second (u_nom = NULL) starts from the
+    first one's shifted result"""
+    p = W.random_small(70, S=2000, T=20, n_obs=3)
+    ctx.set_path(400, p.path, p.ds)
+    t1, _ = B.brmppi_submit(ctx.h, B.ProblemBuffers(p, controller=400))
+    p2 = p.copy(seed=p.seed + 1)
+    t2, _ = B.brmppi_submit(ctx.h, B.ProblemBuffers(p2, controller=400, with_nominal=False))
+    u1, _, _ = B.brmppi_wait(ctx.h, t1, p.T)
+    u2, _, _ = B.brmppi_wait(ctx.h, t2, p.T)
+    # replay with the plain path
+    ctx.set_path(401, p.path, p.ds)
+    v1, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=401))
+    v2, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p2, controller=401, with_nominal=False))
+    assert np.array_equal(u1, v1) and np.array_equal(u2, v2)
+    # consumed / unknown tickets
+    with pytest.raises(B.BrmppiError) as e:
+        B.brmppi_poll(ctx.h, t1, p.T)
+    assert e.value.code == B.ENOTICKET
+
+
+def test_served_closed_loop_on_device(ctx):
+    """X0_RESIDENT | ADVANCE_PLANT requests == brmppi_closed_loop, bitwise"""
+    p = W.random_small(71, S=1500, T=15, n_obs=4)
+    ctx.set_path(402, p.path, p.ds)
+    ctx.set_path(403, p.path, p.ds)
+    K = 5
+    x_cl, u_cl = B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=402), K)
+    B.brmppi_set_state(ctx.h, 403, p.x0.astype(np.float64))
+    flags = p.flags | B.X0_RESIDENT | B.ADVANCE_PLANT
+    outs = []
+    for k in range(K):
+        pb = B.ProblemBuffers(p, controller=403, with_nominal=(k == 0), flags=flags, seed=p.seed + k)
+        t, _ = B.brmppi_submit(ctx.h, pb)
+        outs.append(B.brmppi_wait(ctx.h, t, p.T)[0])
+    assert np.array_equal(np.array([o[0] for o in outs]), u_cl)
+    assert np.array_equal(B.brmppi_get_state(ctx.h, 403), x_cl[-1])
+
+
+def test_closed_loop_matches_plain_and_oracle_plant(ctx):
+    from oracle import oracle as O
+    p = W.config2().copy(S=2048, T=30)
+    ctx.set_path(404, p.path, p.ds)
+    ctx.set_path(405, p.path, p.ds)
+    K = 4
+    x_cl, u_cl = B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=404), K)
+    assert np.all(np.isfinite(x_cl))
+    u0, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=405))
+    assert np.array_equal(u0[0], u_cl[0])
+    for k in range(K):
+        want = O.plant_step(x_cl[k], u_cl[k], p.params)
+        assert np.allclose(x_cl[k + 1], want, rtol=1e-14, atol=1e-14), k
+
+
+def test_autotune_keeps_results(ctx, tmp_path):
+    p = W.random_small(80, S=3000, T=12, n_obs=7)
+    ctx.set_path(406, p.path, p.ds)
+    before = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=406))[0]
+    B.brmppi_autotune(ctx.h)
+    for block in (64, 128, 256):
+        B.brmppi_set_launch(ctx.h, block, 1)
+        after = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=406))[0]
+        assert np.array_equal(before, after), block
+    B.brmppi_set_launch(ctx.h, 0, 1)
+
+
+def test_invalid_arguments_leave_state(ctx):
+    p = W.random_small(81, S=100, T=5, n_obs=1)
+    ctx.set_path(407, p.path, p.ds)
+    good = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=407))[0]
+    bad = p.copy(lam=-1.0)
+    with pytest.raises(B.BrmppiError) as e:
+        B.brmppi_solve(ctx.h, B.ProblemBuffers(bad, controller=407))
+    assert e.value.code == B.EINVAL
+    obs = p.obstacles.copy()
+    obs[0, 5] = 4.0                          # e = 4 is not implemented
+    with pytest.raises(B.BrmppiError) as e:
+        B.brmppi_solve(ctx.h, B.ProblemBuffers(p.copy(obstacles=obs), controller=407))
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BrmppiError) as e:      # no warm start of that length
+        B.brmppi_solve(ctx.h, B.ProblemBuffers(p.copy(T=7, u_nom=np.zeros((7, 3), np.float32)), controller=408,
+                                               with_nominal=False))
+    assert e.value.code in (B.ESTATE,)
+    # the warm start of 407 is unchanged by the failed calls
+    assert np.array_equal(B.brmppi_get_nominal(ctx.h, 407, p.T), np.concatenate([good[1:], good[-1:]]))
