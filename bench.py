@@ -49,8 +49,16 @@ def flops_per_sample_step(n_obs: int, hitch: bool = True, guided: bool = True) -
     return base + 24 * nb + (120 if hitch else 0) + 125 * n_obs
 
 
-def rollout_flops(S: int, T: int, n_obs: int, hitch=True, guided=True) -> float:
-    return float(S) * (T * flops_per_sample_step(n_obs, hitch, guided) + 48)
+def noise_flops_per_sample_step(n_obs: int, guided: bool = True) -> int:
+    """Box-Muller part of the count (24 per Philox block)"""
+    return 24 * ((5 + n_obs + 3) // 4 if guided else 1)
+
+
+def rollout_flops(S: int, T: int, n_obs: int, hitch=True, guided=True, noise_in_kernel=True) -> float:
+    f = flops_per_sample_step(n_obs, hitch, guided)
+    if not noise_in_kernel:
+        f -= noise_flops_per_sample_step(n_obs, guided)
+    return float(S) * (T * f + 48)
 
 
 def kernel_sha() -> str:
@@ -89,6 +97,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true", help="only the timed closed loop")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
+    ap.add_argument("--tune-file", default=None,
+                    help="launch-shape table: used as is when it exists, else written by the autotune")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -116,9 +127,19 @@ def main():
 
     prob = W.config2()
     S, T, n_obs = prob.S, prob.T, prob.n_obs
+    import tempfile
+
+    tune_file = args.tune_file or os.path.join(tempfile.mkdtemp(prefix="brmppi_tune_"), "launch.json")
+    have_table = os.path.exists(tune_file)
     ctx = B.Context(arena_bytes=3 << 30, n_streams=2, max_controllers=600,
-                    profile=False, flags_extra=B.CTX_PROFILE_ROLLOUT)
+                    profile=False, flags_extra=B.CTX_PROFILE_ROLLOUT, autotune_cache=tune_file)
     h = ctx.h
+    shape = None
+    if not args.no_autotune:
+        if not have_table:
+            note("autotuning launch shapes")
+            B.brmppi_autotune(h)
+        shape = json.load(open(tune_file)).get("plain_8_1")   # 8-obstacle bucket, S <= 8192
     ctx.set_path(0, prob.path, prob.ds)
     pb = B.ProblemBuffers(prob, controller=0)
 
@@ -135,7 +156,11 @@ def main():
     x_end = B.brmppi_get_state(h, 0)
     value = S * T * args.steps / wall
     roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
-    flops = rollout_flops(S, T, n_obs)
+    noise_ms = prof["noise"]["ms"] / prof["noise"]["count"] if prof["noise"]["count"] else 0.0
+    # variants 1-3 draw the normals in the separate noise kernel: the rollout
+    # kernel's own algorithmic work then excludes the Box-Muller flops
+    noise_in_kernel = prof["noise"]["count"] == 0
+    flops = rollout_flops(S, T, n_obs, noise_in_kernel=noise_in_kernel)
     achieved = flops / (roll_ms * 1e-3) / 1e12
     traffic = load_traffic()
     out = {
@@ -159,7 +184,8 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-            "kernel": "k_rollout<8,true>", "flops_per_launch": flops, "avg_launch_ms": roll_ms,
+            "kernel": "k_rollout (8-obstacle bucket)", "launch_shape": {"block_variant": shape},
+            "noise_kernel_avg_ms": noise_ms, "flops_per_launch": flops, "avg_launch_ms": roll_ms,
             "launches": prof["rollout"]["count"], "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
             "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
             "flops_per_sample_step": flops_per_sample_step(n_obs),

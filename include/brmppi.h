@@ -68,7 +68,7 @@ extern "C" {
 
 /* ---- context flags ------------------------------------------------------ */
 #define BRMPPI_CTX_PROFILE 1u     /* time every kernel of the blocking calls with HIP events */
-#define BRMPPI_CTX_PROFILE_ROLLOUT 2u /* time only the rollout kernel (lower overhead) */
+#define BRMPPI_CTX_PROFILE_ROLLOUT 2u /* time only the rollout and noise kernels (lower overhead) */
 
 typedef struct brmppi_ctx brmppi_ctx;
 
@@ -210,16 +210,24 @@ int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_upda
                        float* u_applied);
 
 /* ---- launch shapes / profiling ------------------------------------------ */
-/* Time the rollout kernel for each candidate launch shape on synthetic
- * problems and keep the fastest per constraint bucket; writes the JSON cache
- * named in the config (if any).  Shapes never change results. */
+/* Time the rollout for each candidate launch shape (block size and variant:
+ * samples per wave, noise drawn in the kernel or by a separate parallel
+ * kernel) on synthetic problems and keep the fastest per constraint bucket
+ * (0, <=2, <=8, <=16, <=32 obstacles) and sample-count class (<=2048, <=8192,
+ * <=32768, more), plus the block size of the batched persistent kernel;
+ * writes the JSON cache named in the config (if any).  Shapes never change a
+ * result bit. */
 int brmppi_autotune(brmppi_ctx* ctx);
-/* Force a rollout launch shape (block size 64..1024, lanes per sample 1, 2, 4
- * or 8) for every bucket; 0 restores the tuned/default choice. */
-int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t lanes_per_sample);
+/* Force a rollout launch shape for every plain and batched launch: block size
+ * 64..256 (multiple of 64) and variant 0 = one lane per sample, noise drawn in
+ * the kernel; 1 = one lane, noise from the parallel kernel; 2 / 3 = two / four
+ * lanes per sample, noise from the parallel kernel (batched launches always
+ * use variant 0).  block 0 restores the tuned/default choice. */
+int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant);
 /* Kernel timings accumulated under BRMPPI_CTX_PROFILE (ms totals and counts):
- * out[0..1] rollout, out[2..3] weights, out[4..5] reduce, out[6..7] plant. */
-int brmppi_profile_read(brmppi_ctx* ctx, double out[8]);
+ * out[0..1] rollout, out[2..3] reduce (weights + average + shift + plant),
+ * out[4..5] noise. */
+int brmppi_profile_read(brmppi_ctx* ctx, double out[6]);
 int brmppi_profile_reset(brmppi_ctx* ctx);
 
 /* ---- debug entry points (parity tests) ---------------------------------- */

@@ -280,14 +280,16 @@ def brmppi_autotune(ctx):
     return check(lib().brmppi_autotune(ctx))
 
 
-def brmppi_set_launch(ctx, block, lanes=1):
-    return check(lib().brmppi_set_launch(ctx, int(block), int(lanes)))
+def brmppi_set_launch(ctx, block, variant=0):
+    """variant: 0 one lane per sample (in-kernel noise), 1 one lane (noise kernel),
+    2 / 3 two / four lanes per sample (noise kernel); block 0 = tuned default"""
+    return check(lib().brmppi_set_launch(ctx, int(block), int(variant)))
 
 
 def brmppi_profile_read(ctx):
-    out = np.zeros(8)
+    out = np.zeros(6)
     check(lib().brmppi_profile_read(ctx, _dp(out)))
-    names = ("rollout", "weights", "reduce", "plant")
+    names = ("rollout", "reduce", "noise")
     return {n: dict(ms=out[2 * i], count=out[2 * i + 1]) for i, n in enumerate(names)}
 
 

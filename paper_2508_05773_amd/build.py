@@ -20,11 +20,14 @@ HEADERS = ["brmppi_internal.h"]
 ARCH = os.environ.get("BRMPPI_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for the whole library: hipcc -O3 would
-# otherwise form v_pk_* FP32 ops from ordinary float code.
+# otherwise form v_pk_* FP32 ops from ordinary float code.  FMAs are formed only
+# within one source expression (-ffp-contract=on), so every kernel variant that
+# inlines the same row code rounds it the same way (results do not depend on
+# the launch shape).
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-fno-gpu-rdc", "-Wall", "-Wno-unused-function",
+    "-ffp-contract=on", "-fno-gpu-rdc", "-Wall", "-Wno-unused-function",
     "-Wno-unused-variable", "-Wno-unused-but-set-variable",
 ]
 

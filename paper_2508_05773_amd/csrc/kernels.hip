@@ -1,24 +1,25 @@
 // gfx950 kernels of one BR-MPPI control update (arXiv 2508.05773).
 //
-//   k_rollout : counter-based noise + S rollouts of the tractor-trailer model,
-//               each step projected onto the barrier-rate equalities (eq. (9))
-//               with the soft-bound closed form (eqs. (11)-(12)), contouring
-//               cost (eqs. (13)-(15)) accumulated; writes the applied inputs
-//               [3T][S] and the cost of every sample.
-//   k_weights : per 1024-sample chunk, min cost and sum of
-//               exp(-(J - m_chunk)/lambda) (Sec. III-B weights).
-//   k_reduce  : chunk partials of sum_s gamma_s u*_s for every (step, input)
-//               row, then the last block of the instance merges the chunks
-//               (log-sum-exp rescaling), writes the new nominal sequence
-//               (eq. (5)) and the receding-horizon shift (Sec. III-B).
-//   k_plant   : closed-loop helper: advance a resident FP64 plant by the first
-//               averaged input (eq. (6)).
+//   k_noise   : Philox4x32-10 + Box-Muller normals of every (sample, step)
+//               in parallel (for the rollout variants that read them).
+//   k_rollout : S rollouts of the tractor-trailer model, each step projected
+//               onto the barrier-rate equalities (eq. (9)) with the
+//               soft-bound closed form (eqs. (11)-(12)), contouring cost
+//               (eqs. (13)-(15)) accumulated; writes the applied inputs
+//               [3T][S] and the cost of every sample.  One or several lanes
+//               per sample; noise drawn in the kernel or read from k_noise.
+//   k_reduce  : per 1024-sample chunk, the min cost and the weights
+//               exp(-(J - m_chunk)/lambda) (Sec. III-B), chunk partials of
+//               sum_s gamma_s u*_s for every (step, input) row; the last block
+//               of the instance merges the chunks (log-sum-exp rescaling),
+//               writes the new nominal sequence (eq. (5)), the receding-horizon
+//               shift and, on request, a closed-loop FP64 plant step (eq. (6)).
 //
-// One lane owns one sample; its state, barrier rates and row terms stay in
-// registers.  Obstacles (with their shape matrices) and a window of the path
-// are staged in LDS per tile.  Positions are carried relative to the start
-// position and progress relative to the start progress so that FP32 keeps
-// sub-micrometre resolution far from the origin.
+// A sample's state, barrier rates and row terms stay in registers.  Obstacles
+// (with their shape matrices) and a window of the path are staged in LDS per
+// tile.  Positions are carried relative to the start position and progress
+// relative to the start progress so that FP32 keeps sub-micrometre resolution
+// far from the origin.
 #include <math.h>
 
 #include "brmppi_internal.h"
@@ -141,12 +142,124 @@ __device__ __forceinline__ float tracking_cost(const brmppi_params& P, const Ref
 // ---------------------------------------------------------------------------
 // Rollout
 // ---------------------------------------------------------------------------
-template <int NOB, bool GUIDED>
-__device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, const float* x0,
+// Launch shapes: G lanes share one sample (G = 1, 2, 4).  Every lane of a group
+// carries the full state; obstacle o's barrier row is computed by group lane
+// o % G, and its projection terms are broadcast to the group with DPP quad
+// permutes, so that every lane accumulates all rows in the same canonical
+// order (hitch+, hitch-, obstacles) as a one-lane sample does.  With PRE the
+// normals come from the noise buffer filled by k_noise (same Philox and
+// Box-Muller code) instead of being drawn in the rollout.  Results are
+// therefore bitwise identical for every (G, PRE) and block size.
+
+struct ProjConst {
+  float Ma, inv_Ma, amid, h_eps, W_a, rho;
+};
+
+// projection terms of one row of eq. (9) after eliminating its auxiliary
+// input: (M_u + c g g') u = ... + c g rr, and the quantities the next barrier
+// rate needs
+struct RowTerms {
+  float c, g0, g1, rr, Lf, ih;
+};
+
+__device__ __forceinline__ RowTerms row_terms(const ProjConst& K, float hhat, float Lf, float g0, float g1,
+                                              float atil, float alpha) {
+  const float ah = fabsf(hhat);
+  const float hh = (ah < K.h_eps) ? (hhat < 0.0f ? -K.h_eps : K.h_eps) : hhat;
+  const float b = -Lf - alpha * hh;
+  const float abar = (K.W_a * atil + K.rho * (K.amid - alpha)) * K.inv_Ma;
+  RowTerms R;
+  R.rr = b - hh * abar;
+  R.ih = rcp(hh);
+  R.c = K.Ma * R.ih * R.ih;
+  R.g0 = g0;
+  R.g1 = g1;
+  R.Lf = Lf;
+  return R;
+}
+
+// 2x2 normal equations of the eliminated projection, accumulated in FP64
+struct Normal2 {
+  double N00, N01, N11, y0, y1;
+};
+
+__device__ __forceinline__ void accumulate(Normal2& A, float c, float g0, float g1, float rr) {
+  const double cg0 = (double)c * (double)g0, cg1 = (double)c * (double)g1;
+  A.N00 = fma(cg0, (double)g0, A.N00);
+  A.N01 = fma(cg0, (double)g1, A.N01);
+  A.N11 = fma(cg1, (double)g1, A.N11);
+  A.y0 = fma(cg0, (double)rr, A.y0);
+  A.y1 = fma(cg1, (double)rr, A.y1);
+}
+
+// obstacle row, eqs. (16)-(17) with e = 2: with q = d + Ts d_dot,
+// hhat = q'Qq - 1 + Ts^2 d'Q d_ddot; Lf and g along f = Ts f_c, g = Ts g_c
+struct ObsRow {
+  float hhat, Lf, g0, g1;
+};
+
+__device__ __forceinline__ ObsRow obstacle_row(const ObsL& ob, float px, float py, float v, float a, float c1,
+                                               float s1, float vkd, float sec2, float t, float Ts, float Ts2,
+                                               float inv_l1) {
+  const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
+  const float ddx = v * c1 - ob.vx, ddy = v * s1 - ob.vy;
+  const float v2kd = v * vkd;
+  const float dddx = a * c1 - v2kd * s1, dddy = a * s1 + v2kd * c1;
+  const float qx = dx + Ts * ddx, qy = dy + Ts * ddy;
+  const float Qqx = ob.q11 * qx + ob.q12 * qy, Qqy = ob.q12 * qx + ob.q22 * qy;
+  const float Qdx = ob.q11 * dx + ob.q12 * dy, Qdy = ob.q12 * dx + ob.q22 * dy;
+  const float dQe1 = Qdx * c1 + Qdy * s1, dQe2 = Qdy * c1 - Qdx * s1;
+  const float qQe1 = Qqx * c1 + Qqy * s1, qQe2 = Qqy * c1 - Qqx * s1;
+  // gradient of hhat: position, speed, heading, time
+  const float gpx = 2.0f * Qqx + Ts2 * (ob.q11 * dddx + ob.q12 * dddy);
+  const float gpy = 2.0f * Qqy + Ts2 * (ob.q12 * dddx + ob.q22 * dddy);
+  const float h_v = 2.0f * Ts * qQe1 + 2.0f * Ts2 * vkd * dQe2;
+  const float h_th = 2.0f * Ts * v * qQe2 + Ts2 * (a * dQe2 - v2kd * dQe1);
+  const float h_t = -(gpx * ob.vx + gpy * ob.vy);
+  ObsRow R;
+  R.hhat = qx * Qqx + qy * Qqy - 1.0f + Ts2 * (Qdx * dddx + Qdy * dddy);
+  R.Lf = Ts * (v * (gpx * c1 + gpy * s1) + h_v * a + h_th * vkd + h_t);
+  R.g0 = Ts * Ts2 * dQe1;                          // Ts d hhat/da
+  R.g1 = Ts * Ts2 * v * v * sec2 * inv_l1 * dQe2;   // Ts d hhat/d delta
+  return R;
+}
+
+// value held by lane Q of each G-lane group, broadcast to the group (DPP quad
+// permute; G divides 4 so a group never crosses a quad)
+template <int G, int Q>
+__device__ __forceinline__ float group_bcast(float x) {
+  if constexpr (G == 1) {
+    return x;
+  } else {
+    constexpr int ctrl = (G == 4) ? (Q * 0x55) : ((Q) | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6));
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), ctrl, 0xF, 0xF, false));
+  }
+}
+
+template <int G>
+__device__ __forceinline__ float group_bcast_dyn(float x, int q) {
+  // q is a compile-time constant at every call site after unrolling
+  switch (q) {
+    case 0: return group_bcast<G, 0>(x);
+    case 1: return group_bcast<G, (G > 1 ? 1 : 0)>(x);
+    case 2: return group_bcast<G, (G > 2 ? 2 : 0)>(x);
+    default: return group_bcast<G, (G > 3 ? 3 : 0)>(x);
+  }
+}
+
+// normals k of (s, tau) in the noise buffer [tau][k][S_pad]
+__device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t tau, uint32_t k) {
+  return d.noise + ((size_t)tau * d.n_normals + k) * d.S_pad;
+}
+
+template <int NOB, bool GUIDED, int G, bool PRE>
+__device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
                                                int w0, int nw, int k0, float phi0) {
-  constexpr int NR = NOB + 2;                       // rows: hitch+, hitch-, obstacles
-  constexpr int NBMAX = GUIDED ? (5 + NOB + 3) / 4 : 1;
+  static_assert(G == 1 || G == 2 || G == 4, "lanes per sample");
+  static_assert(PRE || G == 1, "a sample shared by lanes reads precomputed normals");
+  constexpr int NSL = GUIDED ? (NOB + G - 1) / G : 1;   // obstacle slots of this lane
+  constexpr int NBMAX = GUIDED ? (5 + NOB + 3) / 4 : 1;  // Philox blocks (fused noise)
   const brmppi_params& P = d.prm;
   const float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
   const float inv_l1 = 1.0f / P.l1, inv_l2 = 1.0f / P.l2, ch = P.lh / P.l1;
@@ -161,35 +274,80 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
 
   // soft-bound projection constants, eq. (11): M = W + rho I,
   // p = W z_des + rho/2 (lo + hi)
-  const float Mj = P.W_j + P.rho, Mw = P.W_w + P.rho, Ma = P.W_a + P.rho;
-  const float inv_Ma = 1.0f / Ma;
+  ProjConst K;
+  K.Ma = P.W_a + P.rho;
+  K.inv_Ma = 1.0f / K.Ma;
+  K.amid = 0.5f * (P.alpha_lo + P.alpha_hi);
+  K.h_eps = P.h_eps;
+  K.W_a = P.W_a;
+  K.rho = P.rho;
+  const float Mj = P.W_j + P.rho, Mw = P.W_w + P.rho;
   const float pj0 = 0.5f * P.rho * (P.j_lo + P.j_hi);
   const float pw0 = 0.5f * P.rho * (P.w_lo + P.w_hi);
-  const float amid = 0.5f * (P.alpha_lo + P.alpha_hi);
 
   float px = 0.0f, py = 0.0f, v = x0[2], a = x0[3], th1 = x0[4], th2 = x0[5], dl = x0[6], psi = 0.0f;
-  float alpha[NR];
+  float alpha_h[2] = {P.alpha0, P.alpha0};
+  float alpha_o[NSL];
 #pragma unroll
-  for (int i = 0; i < NR; ++i) alpha[i] = P.alpha0;
+  for (int j = 0; j < NSL; ++j) alpha_o[j] = P.alpha0;
   double J = 0.0;
   const uint32_t S_pad = d.S_pad;
   float* __restrict__ ustar = d.u_star;
   const float* __restrict__ unom = d.u_nom_in;
 
-  for (uint32_t tau = 0; tau < d.T; ++tau) {
-    // --- noise (Philox counter (s, tau, block, instance), key = seed) ---
-    float eps[4 * NBMAX];
+  // precomputed normals of the next step (prefetched one step ahead)
+  float nx_in[3], nx_h[2], nx_o[NSL];
+  auto load_normals = [&](uint32_t tau) {
+    if constexpr (PRE) {
 #pragma unroll
-    for (int b = 0; b < NBMAX; ++b) {
-      if (b < nb) {
-        uint32_t r[4];
-        philox4x32_10(s, tau, (uint32_t)b, d.instance, d.seed_lo, d.seed_hi, r);
-        box_muller4(r, &eps[4 * b]);
+      for (int k = 0; k < 3; ++k) nx_in[k] = noise_row(d, tau, k)[s];
+      if (guided) {
+        nx_h[0] = noise_row(d, tau, 3)[s];
+        nx_h[1] = noise_row(d, tau, 4)[s];
+#pragma unroll
+        for (int j = 0; j < NSL; ++j) {
+          const int o = g + G * j;
+          nx_o[j] = (o < n_obs) ? noise_row(d, tau, 5 + o)[s] : 0.0f;
+        }
       }
     }
-    float uj = unom[3 * tau + 0] + P.sigma_j * eps[0];
-    float uw = unom[3 * tau + 1] + P.sigma_w * eps[1];
-    const float unu = unom[3 * tau + 2] + P.sigma_nu * eps[2];
+  };
+  if constexpr (PRE) load_normals(0);
+
+  for (uint32_t tau = 0; tau < d.T; ++tau) {
+    // --- noise: normals 0..2 perturb the inputs, 3 and 4 the hitch rows'
+    // auxiliary inputs, 5 + o obstacle o's ---
+    float e_in[3], e_h[2], e_o[NSL];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e_in[k] = nx_in[k];
+      e_h[0] = nx_h[0];
+      e_h[1] = nx_h[1];
+#pragma unroll
+      for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[j];
+      if (tau + 1 < d.T) load_normals(tau + 1);
+    } else {
+      float eps[4 * NBMAX];
+#pragma unroll
+      for (int b = 0; b < NBMAX; ++b) {
+        if (b < nb) {
+          uint32_t r[4];
+          philox4x32_10(s, tau, (uint32_t)b, d.instance, d.seed_lo, d.seed_hi, r);
+          box_muller4(r, &eps[4 * b]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e_in[k] = eps[k];
+      if constexpr (GUIDED) {
+        e_h[0] = eps[3];
+        e_h[1] = eps[4];
+#pragma unroll
+        for (int j = 0; j < NSL; ++j) e_o[j] = eps[5 + j];   // G == 1: slot j is obstacle j
+      }
+    }
+    float uj = unom[3 * tau + 0] + P.sigma_j * e_in[0];
+    float uw = unom[3 * tau + 1] + P.sigma_w * e_in[1];
+    const float unu = unom[3 * tau + 2] + P.sigma_nu * e_in[2];
 
     float s1, c1, sp, cp;
     sincosf(th1, &s1, &c1);
@@ -202,34 +360,16 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
     if (GUIDED && guided) {
       const float sec2 = 1.0f + tn * tn;
       const float t = d.t0 + (float)tau * Ts;
-      // 2x2 normal equations of the eliminated projection, in FP64:
-      // (M_u + sum c_i g_i g_i') u = p_u + sum c_i g_i r_i
-      double N00 = Mj, N01 = 0.0, N11 = Mw;
-      double y0 = (double)(P.W_j * uj + pj0), y1 = (double)(P.W_w * uw + pw0);
-      float rLf[NR], rg0[NR], rg1[NR], rih[NR];
-
-      auto accumulate = [&](int i, float hhat, float Lf, float g0, float g1, float atil) {
-        const float ah = fabsf(hhat);
-        const float hh = (ah < P.h_eps) ? (hhat < 0.0f ? -P.h_eps : P.h_eps) : hhat;
-        const float b = -Lf - alpha[i] * hh;
-        const float abar = (P.W_a * atil + P.rho * (amid - alpha[i])) * inv_Ma;
-        const float rr = b - hh * abar;
-        const float ih = rcp(hh);
-        const float c = Ma * ih * ih;
-        const double cg0 = (double)c * (double)g0, cg1 = (double)c * (double)g1;
-        N00 = fma(cg0, (double)g0, N00);
-        N01 = fma(cg0, (double)g1, N01);
-        N11 = fma(cg1, (double)g1, N11);
-        y0 = fma(cg0, (double)rr, y0);
-        y1 = fma(cg1, (double)rr, y1);
-        rLf[i] = Lf;
-        rg0[i] = g0;
-        rg1[i] = g1;
-        rih[i] = ih;
-      };
+      Normal2 A;
+      A.N00 = Mj;
+      A.N01 = 0.0;
+      A.N11 = Mw;
+      A.y0 = (double)(P.W_j * uj + pj0);
+      A.y1 = (double)(P.W_w * uw + pw0);
 
       // hitch rows, eq. (18) split into h_s = dth_max - kappa v + s (th1 - th2),
-      // first-order expansion hhat = h + Ts hd
+      // first-order expansion hhat = h + Ts hd (every lane computes both)
+      RowTerms H[2];
       if (hitch) {
         const float D = v * inv_l2 * Aw2 - vkd;                 // th2_dot - th1_dot
         const float D_v = inv_l2 * Aw2 - kd;
@@ -243,48 +383,46 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
           const float hd = -P.kappa * a - sg * D;
           const float hv = -P.kappa - sg * Ts * D_v;
           const float Lf = Ts * (hv * a - sg * (1.0f - Ts * D_phi) * D);
-          accumulate(k, h + Ts * hd, Lf, -P.kappa * Ts2, -sg * Ts2 * D_dl, P.sigma_a * eps[3 + k]);
+          H[k] = row_terms(K, h + Ts * hd, Lf, -P.kappa * Ts2, -sg * Ts2 * D_dl, P.sigma_a * e_h[k], alpha_h[k]);
+          accumulate(A, H[k].c, H[k].g0, H[k].g1, H[k].rr);
         }
       }
-      // obstacle rows, eqs. (16)-(17): with q = d + Ts d_dot,
-      // hhat = q'Qq - 1 + Ts^2 d'Q d_ddot
+      // obstacle rows of this lane's slots
+      RowTerms O[NSL];
+#pragma unroll
+      for (int j = 0; j < NSL; ++j) {
+        const int o = (G == 1) ? j : g + G * j;
+        if (o < n_obs) {
+          const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+          O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+        } else {
+          O[j].c = O[j].g0 = O[j].g1 = O[j].rr = O[j].Lf = O[j].ih = 0.0f;
+        }
+      }
+      // every lane accumulates every obstacle row in obstacle order
 #pragma unroll
       for (int o = 0; o < NOB; ++o) {
         if (o < n_obs) {
-          const ObsL ob = sobs[o];
-          const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
-          const float ddx = v * c1 - ob.vx, ddy = v * s1 - ob.vy;
-          const float v2kd = v * vkd;
-          const float dddx = a * c1 - v2kd * s1, dddy = a * s1 + v2kd * c1;
-          const float qx = dx + Ts * ddx, qy = dy + Ts * ddy;
-          const float Qqx = ob.q11 * qx + ob.q12 * qy, Qqy = ob.q12 * qx + ob.q22 * qy;
-          const float Qdx = ob.q11 * dx + ob.q12 * dy, Qdy = ob.q12 * dx + ob.q22 * dy;
-          const float hhat = qx * Qqx + qy * Qqy - 1.0f + Ts2 * (Qdx * dddx + Qdy * dddy);
-          const float dQe1 = Qdx * c1 + Qdy * s1, dQe2 = Qdy * c1 - Qdx * s1;
-          const float qQe1 = Qqx * c1 + Qqy * s1, qQe2 = Qqy * c1 - Qqx * s1;
-          // gradient of hhat: position, speed, heading, time
-          const float gpx = 2.0f * Qqx + Ts2 * (ob.q11 * dddx + ob.q12 * dddy);
-          const float gpy = 2.0f * Qqy + Ts2 * (ob.q12 * dddx + ob.q22 * dddy);
-          const float h_v = 2.0f * Ts * qQe1 + 2.0f * Ts2 * vkd * dQe2;
-          const float h_th = 2.0f * Ts * v * qQe2 + Ts2 * (a * dQe2 - v2kd * dQe1);
-          const float h_t = -(gpx * ob.vx + gpy * ob.vy);
-          const float Lf = Ts * (v * (gpx * c1 + gpy * s1) + h_v * a + h_th * vkd + h_t);
-          const float g0 = Ts * Ts2 * dQe1;                          // Ts d hhat/da
-          const float g1 = Ts * Ts2 * v * v * sec2 * inv_l1 * dQe2;   // Ts d hhat/d delta
-          accumulate(2 + o, hhat, Lf, g0, g1, P.sigma_a * eps[5 + o]);
+          const int j = o / G, q = o % G;
+          accumulate(A, group_bcast_dyn<G>(O[j].c, q), group_bcast_dyn<G>(O[j].g0, q),
+                     group_bcast_dyn<G>(O[j].g1, q), group_bcast_dyn<G>(O[j].rr, q));
         }
       }
-      const double det = N00 * N11 - N01 * N01;
+      const double det = A.N00 * A.N11 - A.N01 * A.N01;
       const double idet = 1.0 / det;
-      const double u0 = (N11 * y0 - N01 * y1) * idet;
-      const double u1 = (N00 * y1 - N01 * y0) * idet;
+      const double u0 = (A.N11 * A.y0 - A.N01 * A.y1) * idet;
+      const double u1 = (A.N00 * A.y1 - A.N01 * A.y0) * idet;
       uj = (float)u0;
       uw = (float)u1;
       // next barrier rates: alpha + u*alpha = -(Lf + g u*)/hh (eq. (9) holds exactly)
+      if (hitch) {
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const bool on = (i < 2) ? hitch : (i - 2 < n_obs);
-        if (on) alpha[i] = -(rLf[i] + rg0[i] * uj + rg1[i] * uw) * rih[i];
+        for (int k = 0; k < 2; ++k) alpha_h[k] = -(H[k].Lf + H[k].g0 * uj + H[k].g1 * uw) * H[k].ih;
+      }
+#pragma unroll
+      for (int j = 0; j < NSL; ++j) {
+        const int o = (G == 1) ? j : g + G * j;
+        if (o < n_obs) alpha_o[j] = -(O[j].Lf + O[j].g0 * uj + O[j].g1 * uw) * O[j].ih;
       }
     }
 
@@ -296,9 +434,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
     J += (double)rc;
 
     // --- applied inputs [3T][S_pad] ---
-    ustar[(size_t)(3 * tau + 0) * S_pad + s] = uj;
-    ustar[(size_t)(3 * tau + 1) * S_pad + s] = uw;
-    ustar[(size_t)(3 * tau + 2) * S_pad + s] = unu;
+    if (store) {
+      ustar[(size_t)(3 * tau + 0) * S_pad + s] = uj;
+      ustar[(size_t)(3 * tau + 1) * S_pad + s] = uw;
+      ustar[(size_t)(3 * tau + 2) * S_pad + s] = unu;
+    }
 
     // --- explicit Euler, eq. (6), plus psi_dot = nu ---
     const float npx = px + Ts * v * c1;
@@ -321,16 +461,17 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, c
   J += (double)tracking_cost(P, rf, px, py, th1, th2);
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
-  d.J[s] = Jf;
+  if (store) d.J[s] = Jf;
 }
 
-template <int NOB, bool GUIDED>
+template <int NOB, bool GUIDED, int G, bool PRE>
 __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restrict__ descs,
                                                        const Tile* __restrict__ tiles, uint32_t n_tiles,
                                                        BatchCounters* __restrict__ ctr) {
   __shared__ float4 s_path[kPathWin];
-  __shared__ ObsL s_obs[BRMPPI_MAX_OBS > 0 ? BRMPPI_MAX_OBS : 1];
+  __shared__ ObsL s_obs[BRMPPI_MAX_OBS];
   __shared__ uint32_t s_tile;
+  const uint32_t per_tile = blockDim.x / G;   // samples per tile
   for (uint32_t it = 0;; ++it) {
     uint32_t tix;
     if (ctr) {
@@ -348,7 +489,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
       tl = tiles[tix];
     } else {
       tl.inst = 0;
-      tl.s0 = tix * blockDim.x;
+      tl.s0 = tix * per_tile;
     }
     const SolveDesc& d = descs[__builtin_amdgcn_readfirstlane(tl.inst)];
 
@@ -400,8 +541,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
     }
     __syncthreads();
 
-    const uint32_t s = tl.s0 + threadIdx.x;
-    if (s < d.S) rollout_sample<NOB, GUIDED>(d, s, x0, s_obs, s_path, w0, nw, k0, phi0);
+    // every lane runs (lanes past S repeat the last sample and do not store),
+    // so the group-wide DPP broadcasts always read active lanes
+    const uint32_t s_raw = tl.s0 + threadIdx.x / G;
+    const int g = (int)(threadIdx.x % G);
+    const bool valid = s_raw < d.S;
+    const uint32_t s = valid ? s_raw : d.S - 1;
+    rollout_sample<NOB, GUIDED, G, PRE>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0);
     __syncthreads();
   }
   if (ctr && threadIdx.x == 0) {
@@ -411,6 +557,25 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
       atomicExch(&ctr->tile_next, 0u);
       atomicExch(&ctr->tile_done, 0u);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Noise: every (sample, step, Philox block) in parallel -> [tau][k][S_pad]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_noise(const SolveDesc* __restrict__ dp) {
+  const SolveDesc& d = *dp;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t tau = blockIdx.y, b = blockIdx.z;
+  if (s >= d.S) return;
+  uint32_t r[4];
+  float e[4];
+  philox4x32_10(s, tau, b, d.instance, d.seed_lo, d.seed_hi, r);
+  box_muller4(r, e);
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t kk = 4 * b + k;
+    if (kk < d.n_normals) d.noise[((size_t)tau * d.n_normals + kk) * d.S_pad + s] = e[k];
   }
 }
 
@@ -455,107 +620,117 @@ __device__ __forceinline__ void finish_persistent(uint32_t* next, uint32_t* done
 }
 
 // ---------------------------------------------------------------------------
-// Weights: per chunk m_c = min J, gamma = exp(-(J - m_c)/lambda), Z_c, Z2_c
+// Weights, weighted reduction and update (Sec. III-B weights, eq. (5))
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWThreads) void k_weights(const SolveDesc* __restrict__ descs,
-                                                      const Item* __restrict__ items, uint32_t n_items,
-                                                      BatchCounters* __restrict__ ctr) {
-  __shared__ float s_red[3][kWThreads / 64];
-  __shared__ uint32_t s_slot;
-  constexpr int PER = kWChunk / kWThreads;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (uint32_t it = 0;; ++it) {
-    uint32_t ix;
-    if (!next_item(it, n_items, ctr ? &ctr->w_next : nullptr, &s_slot, ix)) break;
-    Item item;
-    if (items) item = items[ix];
-    else {
-      item.inst = 0;
-      item.idx = ix;
-    }
-    const SolveDesc& d = descs[__builtin_amdgcn_readfirstlane(item.inst)];
-    const uint32_t base = item.idx * kWChunk;
-    float Jv[PER];
-    float m = INFINITY;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint32_t s = base + threadIdx.x + j * kWThreads;
-      float x = (s < d.S) ? d.J[s] : INFINITY;
-      if (!(x < INFINITY)) x = INFINITY;  // NaN -> +inf (weight 0)
-      Jv[j] = x;
-      m = fminf(m, x);
-    }
-    m = wave_min(m);
-    if (lane == 0) s_red[0][wid] = m;
-    __syncthreads();
-    m = s_red[0][0];
-#pragma unroll
-    for (int w = 1; w < kWThreads / 64; ++w) m = fminf(m, s_red[0][w]);
-    float z = 0.0f, z2 = 0.0f;
-    const bool any = m < INFINITY;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const uint32_t s = base + threadIdx.x + j * kWThreads;
-      const float g = (any && Jv[j] < INFINITY) ? expf(-(Jv[j] - m) * d.inv_lambda) : 0.0f;
-      if (s < d.S) d.gam[s] = g;
-      z += g;
-      z2 += g * g;
-    }
-    z = wave_sum(z);
-    z2 = wave_sum(z2);
-    __syncthreads();
-    if (lane == 0) {
-      s_red[1][wid] = z;
-      s_red[2][wid] = z2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float Z = 0.0f, Z2 = 0.0f;
-#pragma unroll
-      for (int w = 0; w < kWThreads / 64; ++w) {
-        Z += s_red[1][w];
-        Z2 += s_red[2][w];
-      }
-      d.wpart[item.idx] = make_float4(m, Z, Z2, 0.0f);
-    }
-    __syncthreads();
-  }
-  if (ctr) finish_persistent(&ctr->w_next, &ctr->w_done);
-}
+// Work item = (chunk of 1024 samples, group of 4 rows of the [3T][S] applied
+// inputs).  Every block of a chunk recomputes the chunk's weights
+// gamma_s = exp(-(J_s - m_c)/lambda) from the chunk's 4 KB of costs (same code,
+// same order: same values) and stages them in LDS; the first row group also
+// stores (m_c, Z_c, Z2_c).  Wave w sums gamma_s u*[r][s] over the chunk for
+// row r = 4 rg + w with coalesced float4 loads.  The last block of the
+// instance rescales every chunk by exp(-(m_c - m)/lambda) (log-sum-exp merge),
+// writes U_new, the receding-horizon shift and, when asked, the closed-loop
+// plant step.
 
-// ---------------------------------------------------------------------------
-// Reduce: rows of the applied-input tensor weighted by gamma, per chunk; the
-// last block of an instance merges chunks and writes the update + shift.
-// ---------------------------------------------------------------------------
-__device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_misc) {
-  const uint32_t nW = d.n_wchunk;
-  const uint32_t R = 3 * d.T;
-  // merge chunk partials (fixed order)
-  if (threadIdx.x == 0) {
-    float m = INFINITY;
-    for (uint32_t c = 0; c < nW; ++c) m = fminf(m, d.wpart[c].x);
-    float Z = 0.0f, Z2 = 0.0f;
-    if (m < INFINITY) {
-      for (uint32_t c = 0; c < nW; ++c) {
-        const float4 w = d.wpart[c];
-        const float sc = (w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
-        s_scale[c] = sc;
-        Z += sc * w.y;
-        Z2 += sc * sc * w.z;
-      }
-    }
-    s_misc[0] = m;
-    s_misc[1] = Z;
-    s_misc[2] = Z2;
+// FP64 plant step of the closed loop (Sec. II model, inputs clipped to the
+// hard bounds).  The three angles whose sine and cosine it needs go to three
+// lanes of wave 0, one sincos each, so that their latencies overlap.
+__device__ void plant_step(const SolveDesc& d, double* s_trig) {
+  const brmppi_params& P = d.prm;
+  const uint32_t t = threadIdx.x;
+  if (t < 3) {
+    const double* x = d.plant_x;
+    const double ang = t == 0 ? x[4] : (t == 1 ? x[6] : x[4] - x[5]);
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    s_trig[2 * t] = sn;
+    s_trig[2 * t + 1] = cs;
   }
   __syncthreads();
-  const float m = s_misc[0], Z = s_misc[1], Z2 = s_misc[2];
+  if (t == 0) {
+    double x[8];
+    for (int k = 0; k < 8; ++k) x[k] = d.plant_x[k];
+    double j = d.u_new[0], w = d.u_new[1], nu = d.u_new[2];
+    j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
+    w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
+    const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
+    const double v = x[2], a = x[3];
+    const double s1 = s_trig[0], c1 = s_trig[1];
+    const double tan_dl = s_trig[2] / s_trig[3];
+    const double s12 = s_trig[4], c12 = s_trig[5];
+    double xn[8];
+    xn[0] = x[0] + Ts * v * c1;
+    xn[1] = x[1] + Ts * v * s1;
+    xn[2] = v + Ts * a;
+    xn[3] = a + Ts * j;
+    xn[4] = x[4] + Ts * v / l1 * tan_dl;
+    xn[5] = x[5] + Ts * v / l2 * (s12 - lh / l1 * c12 * tan_dl);
+    xn[6] = x[6] + Ts * w;
+    xn[7] = x[7] + Ts * nu;
+    for (int k = 0; k < 8; ++k) d.plant_x[k] = xn[k];
+  }
+}
+
+// block-wide reductions in a fixed order (thread stride, wave butterfly, waves
+// in index order): the same inputs give the same bits on every launch
+__device__ __forceinline__ float block_min(float v, float* s_red) {
+  v = wave_min(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = fminf(r, s_red[w]);
+  return r;
+}
+__device__ __forceinline__ float block_sum(float v, float* s_red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r += s_red[w];
+  return r;
+}
+
+// Merge of the chunk partials by the last block of an instance: global min
+// m = min_c m_c, chunk scale exp(-(m_c - m)/lambda), Z and sum of squared
+// weights, then U = sum_c scale_c rpart[c] / Z per row (eq. (5)).  Every load
+// is issued by a different thread or unrolled, so the merge costs a few memory
+// latencies, not one per chunk.
+__device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_red, double* s_trig) {
+  const uint32_t nW = d.n_wchunk;
+  const uint32_t R = 3 * d.T;
+  const uint32_t nt = blockDim.x;
+  float mloc = INFINITY;
+  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
+    mloc = fminf(mloc, d.wpart[c].x);
+  }
+  const float m = block_min(mloc, s_red);
+  float zl = 0.0f, z2l = 0.0f;
+  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
+    const float4 w = d.wpart[c];
+    const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
+    s_scale[c] = sc;
+    zl += sc * w.y;
+    z2l += sc * sc * w.z;
+  }
+  const float Z = block_sum(zl, s_red);
+  const float Z2 = block_sum(z2l, s_red);   // also orders the s_scale stores before the reads below
   const bool ok = (m < INFINITY) && (Z > 0.0f);
   if (ok) {
     const float iZ = 1.0f / Z;
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) {
+    for (uint32_t r = threadIdx.x; r < R; r += nt) {
+      const float* __restrict__ col = d.rpart + r;
       float acc = 0.0f;
-      for (uint32_t c = 0; c < nW; ++c) acc += s_scale[c] * d.rpart[(size_t)c * R + r];
+      uint32_t c = 0;
+      for (; c + 8 <= nW; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = col[(size_t)(c + k) * R];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += s_scale[c + k] * v[k];
+      }
+      for (; c < nW; ++c) acc += s_scale[c] * col[(size_t)c * R];
       const float U = acc * iZ;
       d.u_new[r] = U;
       // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
@@ -564,7 +739,7 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_m
     }
   } else {
     // every cost non-finite: return the nominal sequence, keep the warm start
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x) d.u_new[r] = d.u_nom_in[r];
+    for (uint32_t r = threadIdx.x; r < R; r += nt) d.u_new[r] = d.u_nom_in[r];
   }
   if (threadIdx.x == 0) {
     d.stats[0] = m;
@@ -572,25 +747,32 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_m
     d.stats[2] = ok ? Z * Z / Z2 : 0.0f;
     d.stats[3] = ok ? (float)BRMPPI_OK : (float)BRMPPI_ENONFINITE;
   }
+  if (d.flags & BRMPPI_ADVANCE_PLANT) {
+    __syncthreads();                 // u_new[0..2] written by threads 0..2
+    plant_step(d, s_trig);
+  }
 }
 
 constexpr uint32_t kMaxWChunks = BRMPPI_MAX_S / kWChunk;
+static_assert(kRowsPerBlock == kWThreads / 64, "one wave per row");
+static_assert(kWChunk == 4 * kWThreads, "one float4 of samples per thread");
 
 __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restrict__ descs,
                                                      const Item* __restrict__ items, uint32_t n_items,
                                                      BatchCounters* __restrict__ ctr) {
-  __shared__ float s_part[kRowsPerBlock][kWThreads / 64];
+  __shared__ float4 s_gam[kWChunk / 4];
+  __shared__ float s_red[3][kWThreads / 64];
   __shared__ float s_scale[kMaxWChunks];
-  __shared__ float s_misc[4];
+  __shared__ double s_trig[6];
   __shared__ uint32_t s_slot, s_last;
-  constexpr int PER = kWChunk / kWThreads;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (uint32_t it = 0;; ++it) {
     uint32_t ix;
     if (!next_item(it, n_items, ctr ? &ctr->r_next : nullptr, &s_slot, ix)) break;
     Item item;
-    if (items) item = items[ix];
-    else {
+    if (items) {
+      item = items[ix];
+    } else {
       item.inst = 0;
       item.idx = ix;
     }
@@ -598,88 +780,97 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     const uint32_t chunk = item.idx / d.n_rgroup, rg = item.idx % d.n_rgroup;
     const uint32_t base = chunk * kWChunk;
     const uint32_t R = 3 * d.T;
-    float g[PER];
-    uint32_t sj[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      sj[j] = base + threadIdx.x + j * kWThreads;
-      g[j] = (sj[j] < d.S) ? d.gam[sj[j]] : 0.0f;
+    const uint32_t S = d.S;
+
+    // --- the chunk's weights (thread t: samples base + 4t .. base + 4t + 3) ---
+    const uint32_t s4 = base + 4 * threadIdx.x;
+    float jv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    if (s4 < d.S_pad) {
+      const float4 q = *reinterpret_cast<const float4*>(d.J + s4);
+      jv[0] = q.x;
+      jv[1] = q.y;
+      jv[2] = q.z;
+      jv[3] = q.w;
     }
-    const uint32_t r0 = rg * kRowsPerBlock;
+    float m = INFINITY;
 #pragma unroll
-    for (int q = 0; q < kRowsPerBlock; ++q) {
-      const uint32_t r = r0 + q;
+    for (int k = 0; k < 4; ++k) {
+      if (!(s4 + k < S) || !(jv[k] < INFINITY)) jv[k] = INFINITY;  // past S or NaN -> weight 0
+      m = fminf(m, jv[k]);
+    }
+    m = wave_min(m);
+    if (lane == 0) s_red[0][wid] = m;
+    __syncthreads();
+    m = s_red[0][0];
+#pragma unroll
+    for (int w = 1; w < kWThreads / 64; ++w) m = fminf(m, s_red[0][w]);
+    const bool any = m < INFINITY;
+    float g[4], z = 0.0f, z2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      g[k] = (any && jv[k] < INFINITY) ? expf(-(jv[k] - m) * d.inv_lambda) : 0.0f;
+      z += g[k];
+      z2 += g[k] * g[k];
+    }
+    s_gam[threadIdx.x] = make_float4(g[0], g[1], g[2], g[3]);
+    if (rg == 0) {
+      z = wave_sum(z);
+      z2 = wave_sum(z2);
+      if (lane == 0) {
+        s_red[1][wid] = z;
+        s_red[2][wid] = z2;
+      }
+    }
+    __syncthreads();
+    if (rg == 0 && threadIdx.x == 0) {
+      float Z = 0.0f, Z2 = 0.0f;
+#pragma unroll
+      for (int w = 0; w < kWThreads / 64; ++w) {
+        Z += s_red[1][w];
+        Z2 += s_red[2][w];
+      }
+      d.wpart[chunk] = make_float4(m, Z, Z2, 0.0f);
+    }
+
+    // --- one wave per row: sum_s gamma_s u*[r][s] over the chunk ---
+    const uint32_t r = rg * kRowsPerBlock + wid;
+    if (r < R) {
+      const float* __restrict__ row = d.u_star + (size_t)r * d.S_pad;
       float acc = 0.0f;
-      if (r < R) {
-        const float* __restrict__ row = d.u_star + (size_t)r * d.S_pad;
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-          if (sj[j] < d.S) acc += g[j] * row[sj[j]];
+      for (int k = 0; k < kWChunk / 4 / 64; ++k) {
+        const uint32_t i4 = lane + 64 * k;
+        const uint32_t s = base + 4 * i4;
+        if (s < d.S_pad) {
+          const float4 u = *reinterpret_cast<const float4*>(row + s);
+          const float4 w = s_gam[i4];
+          // samples past S hold no data: select, never multiply
+          acc += (s + 0 < S) ? w.x * u.x : 0.0f;
+          acc += (s + 1 < S) ? w.y * u.y : 0.0f;
+          acc += (s + 2 < S) ? w.z * u.z : 0.0f;
+          acc += (s + 3 < S) ? w.w * u.w : 0.0f;
+        }
       }
       acc = wave_sum(acc);
-      if (lane == 0) s_part[q][wid] = acc;
+      if (lane == 0) d.rpart[(size_t)chunk * R + r] = acc;
     }
-    __syncthreads();
-    if (threadIdx.x < kRowsPerBlock) {
-      const uint32_t r = r0 + threadIdx.x;
-      if (r < R) {
-        float v = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kWThreads / 64; ++w) v += s_part[threadIdx.x][w];
-        d.rpart[(size_t)chunk * R + r] = v;
-      }
-    }
-    __threadfence();
+    // publish: the barrier completes every wave's stores to this CU's L2
+    // slice, one device-scope fence then makes them visible to the last block
     __syncthreads();
     if (threadIdx.x == 0) {
+      __threadfence();
       const uint32_t k = atomicAdd(d.counter, 1u);
       s_last = (k == d.n_ritems - 1) ? 1u : 0u;
     }
     __syncthreads();
     if (s_last) {
       __threadfence();
-      finalize_instance(d, s_scale, s_misc);
+      finalize_instance(d, s_scale, s_red[0], s_trig);
       if (threadIdx.x == 0) atomicExch(d.counter, 0u);
     }
     __syncthreads();
   }
   if (ctr) finish_persistent(&ctr->r_next, &ctr->r_done);
-}
-
-// ---------------------------------------------------------------------------
-// Closed-loop plant: x <- Euler(x, clamp(U_new[0])) in FP64 (eq. (6))
-// ---------------------------------------------------------------------------
-__device__ void plant_step(const SolveDesc& d) {
-  const brmppi_params& P = d.prm;
-  double x[8];
-  for (int k = 0; k < 8; ++k) x[k] = d.plant_x[k];
-  double j = d.u_new[0], w = d.u_new[1], nu = d.u_new[2];
-  j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
-  w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
-  const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
-  const double v = x[2], a = x[3], t1 = x[4], t2 = x[5], dl = x[6];
-  double xn[8];
-  xn[0] = x[0] + Ts * v * cos(t1);
-  xn[1] = x[1] + Ts * v * sin(t1);
-  xn[2] = v + Ts * a;
-  xn[3] = a + Ts * j;
-  xn[4] = t1 + Ts * v / l1 * tan(dl);
-  xn[5] = t2 + Ts * v / l2 * (sin(t1 - t2) - lh / l1 * cos(t1 - t2) * tan(dl));
-  xn[6] = dl + Ts * w;
-  xn[7] = x[7] + Ts * nu;
-  for (int k = 0; k < 8; ++k) d.plant_x[k] = xn[k];
-}
-
-__global__ void k_plant(const SolveDesc* __restrict__ dp) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  plant_step(*dp);
-}
-
-// batched: one thread per instance, only those that asked for it
-__global__ void k_plant_batch(const SolveDesc* __restrict__ descs, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (descs[i].flags & BRMPPI_ADVANCE_PLANT) plant_step(descs[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,49 +908,85 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t n) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NOB, bool G>
+// rollout variants: 0 = one lane per sample, in-kernel noise; 1 = one lane,
+// precomputed noise; 2 / 3 = two / four lanes per sample, precomputed noise
+int variant_lanes(int variant) { return variant == 2 ? 2 : (variant == 3 ? 4 : 1); }
+bool variant_pre(int variant) { return variant != 0; }
+
+template <int NOB, bool GD, int G, bool PRE>
 static hipError_t launch_rollout_t(const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
                                    BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
-  hipLaunchKernelGGL((k_rollout<NOB, G>), dim3(grid), dim3(block), 0, stream, descs, tiles, n_tiles, ctr);
+  hipLaunchKernelGGL((k_rollout<NOB, GD, G, PRE>), dim3(grid), dim3(block), 0, stream, descs, tiles, n_tiles, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_rollout(int bucket, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
-                          BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
-  if (block == 0 || block > (uint32_t)kMaxBlock || (block % 64) != 0) return hipErrorInvalidValue;
-  switch (bucket) {
-    case 0: return launch_rollout_t<0, false>(descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 2: return launch_rollout_t<2, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 8: return launch_rollout_t<8, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 16: return launch_rollout_t<16, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 32: return launch_rollout_t<32, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+template <int NOB, bool GD>
+static hipError_t launch_variant(int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
+                                 BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
+  switch (variant) {
+    case 0: return launch_rollout_t<NOB, GD, 1, false>(descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 1: return launch_rollout_t<NOB, GD, 1, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 2:
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 2, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      return hipErrorInvalidValue;
+    case 3:
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 4, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NOB, bool G>
+hipError_t launch_rollout(int bucket, int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
+                          BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
+  if (block == 0 || block > (uint32_t)kMaxBlock || (block % 64) != 0) return hipErrorInvalidValue;
+  switch (bucket) {
+    case 0: return launch_variant<0, false>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 2: return launch_variant<2, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 8: return launch_variant<8, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 16: return launch_variant<16, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 32: return launch_variant<32, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NOB, bool GD, int G, bool PRE>
 static int occ_t(uint32_t block) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rollout<NOB, G>, (int)block, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rollout<NOB, GD, G, PRE>, (int)block, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-int rollout_blocks_per_cu(int bucket, uint32_t block) {
-  switch (bucket) {
-    case 0: return occ_t<0, false>(block);
-    case 2: return occ_t<2, true>(block);
-    case 8: return occ_t<8, true>(block);
-    case 16: return occ_t<16, true>(block);
-    default: return occ_t<32, true>(block);
+template <int NOB, bool GD>
+static int occ_variant(int variant, uint32_t block) {
+  switch (variant) {
+    case 1: return occ_t<NOB, GD, 1, true>(block);
+    case 2:
+      if constexpr (GD) return occ_t<NOB, GD, 2, true>(block);
+      return 1;
+    case 3:
+      if constexpr (GD) return occ_t<NOB, GD, 4, true>(block);
+      return 1;
+    default: return occ_t<NOB, GD, 1, false>(block);
   }
 }
 
-hipError_t launch_weights(const SolveDesc* descs, const Item* items, uint32_t n_items, BatchCounters* ctr,
-                          uint32_t grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_weights, dim3(grid), dim3(kWThreads), 0, stream, descs, items, n_items, ctr);
+int rollout_blocks_per_cu(int bucket, int variant, uint32_t block) {
+  switch (bucket) {
+    case 0: return occ_variant<0, false>(variant, block);
+    case 2: return occ_variant<2, true>(variant, block);
+    case 8: return occ_variant<8, true>(variant, block);
+    case 16: return occ_variant<16, true>(variant, block);
+    default: return occ_variant<32, true>(variant, block);
+  }
+}
+
+hipError_t launch_noise(const SolveDesc* desc, uint32_t S, uint32_t T, uint32_t n_normals, hipStream_t stream) {
+  const dim3 grid((S + 255) / 256, T, (n_normals + 3) / 4);
+  hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, stream, desc);
   return hipGetLastError();
 }
+
 
 hipError_t launch_reduce(const SolveDesc* descs, const Item* items, uint32_t n_items, BatchCounters* ctr,
                          uint32_t grid, hipStream_t stream) {
@@ -767,16 +994,7 @@ hipError_t launch_reduce(const SolveDesc* descs, const Item* items, uint32_t n_i
   return hipGetLastError();
 }
 
-hipError_t launch_plant(const SolveDesc* desc, hipStream_t stream) {
-  hipLaunchKernelGGL(k_plant, dim3(1), dim3(64), 0, stream, desc);
-  return hipGetLastError();
-}
 
-hipError_t launch_plant_batch(const SolveDesc* descs, uint32_t n, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plant_batch, dim3((n + 63) / 64), dim3(64), 0, stream, descs, n);
-  return hipGetLastError();
-}
 
 hipError_t launch_philox_dump(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t n, uint32_t* out,
                               hipStream_t stream) {

@@ -145,8 +145,8 @@ struct Controller {
 // layout of one instance's scratch inside a block (off_out: [stats(4) | u_new(3T)]
 // for the plain and closed-loop paths; batches pack their outputs elsewhere)
 struct ScratchLayout {
-  size_t off_ustar, off_J, off_gam, off_wpart, off_rpart, off_out, bytes;
-  uint32_t S_pad, n_wchunk, n_rgroup;
+  size_t off_ustar, off_J, off_wpart, off_rpart, off_out, off_noise, bytes;
+  uint32_t S_pad, n_wchunk, n_rgroup, n_normals;  // n_normals > 0: a noise buffer is included
 };
 
 // one instance's uploaded inputs: [descriptor | reduce counter (zero) | nominal
@@ -163,8 +163,14 @@ InputBlock input_block(uint32_t T, bool with_unom) {
   return b;
 }
 
-ScratchLayout scratch_layout(uint32_t S, uint32_t T) {
+// normals per (sample, step): 3 inputs, 2 hitch rows, one per obstacle
+uint32_t normals_per_step(const brmppi_problem& p) {
+  return (p.flags & BRMPPI_GUIDANCE_OFF) ? 3u : 5u + p.n_obs;
+}
+
+ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0) {
   ScratchLayout L;
+  L.n_normals = noise_normals;
   L.S_pad = (uint32_t)round_up(S, 256);
   L.n_wchunk = (S + kWChunk - 1) / kWChunk;
   L.n_rgroup = (3 * T + kRowsPerBlock - 1) / kRowsPerBlock;
@@ -173,21 +179,24 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T) {
   o = round_up(o + (size_t)3 * T * L.S_pad * sizeof(float), 256);
   L.off_J = o;
   o = round_up(o + (size_t)L.S_pad * sizeof(float), 256);
-  L.off_gam = o;
-  o = round_up(o + (size_t)L.S_pad * sizeof(float), 256);
   L.off_wpart = o;
   o = round_up(o + (size_t)L.n_wchunk * sizeof(float4), 256);
   L.off_rpart = o;
   o = round_up(o + (size_t)L.n_wchunk * 3 * T * sizeof(float), 256);
   L.off_out = o;
   o = round_up(o + (size_t)(4 + 3 * T) * sizeof(float), 256);
+  L.off_noise = o;
+  o = round_up(o + (size_t)noise_normals * T * L.S_pad * sizeof(float), 256);
   L.bytes = o;
   return L;
 }
 
+// largest precomputed-noise buffer a plain solve may take
+constexpr size_t kMaxNoiseBytes = size_t(512) << 20;
+
 struct Profile {
-  double ms[4] = {0, 0, 0, 0};
-  double n[4] = {0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  double n[5] = {0, 0, 0, 0, 0};
 };
 
 struct TimedLaunch {
@@ -219,10 +228,22 @@ struct ServedBatch {
   hipEvent_t done_ev = nullptr;
 };
 
+// rollout launch shape: block size and variant (0 = one lane per sample,
+// in-kernel noise; 1 = one lane, precomputed noise; 2 / 3 = two / four lanes
+// per sample, precomputed noise).  No shape changes any result bit.
 struct LaunchShape {
   uint32_t block = 128;
-  uint32_t lanes = 1;
+  int variant = 0;
 };
+
+constexpr int kBuckets[5] = {0, 2, 8, 16, 32};
+int bucket_index(int bucket) {
+  for (int i = 0; i < 5; ++i)
+    if (kBuckets[i] == bucket) return i;
+  return 4;
+}
+// sample-count classes of the launch table: <= 2048, <= 8192, <= 32768, larger
+int s_class(uint32_t S) { return S <= 2048 ? 0 : (S <= 8192 ? 1 : (S <= 32768 ? 2 : 3)); }
 
 }  // namespace
 
@@ -236,8 +257,9 @@ struct brmppi_ctx {
   int n_cu = 256;
   std::string tune_path;
   std::vector<Controller> ctrl;
-  LaunchShape shape[33];        // indexed by bucket
-  LaunchShape forced;           // block 0 = not forced
+  LaunchShape shape[5][4];      // plain-path table: [bucket index][S class]
+  uint32_t batch_block[5] = {256, 128, 128, 128, 128};  // persistent (variant 0) block per bucket
+  LaunchShape forced{0, 0};     // block 0 = not forced
   Block counters_blk;           // BatchCounters per stream + spare
   BatchCounters* counters = nullptr;
 
@@ -349,19 +371,29 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.u_nom_out = c.unom;
   d.u_star = reinterpret_cast<float*>(base + L.off_ustar);
   d.J = reinterpret_cast<float*>(base + L.off_J);
-  d.gam = reinterpret_cast<float*>(base + L.off_gam);
   d.wpart = reinterpret_cast<float4*>(base + L.off_wpart);
   d.rpart = reinterpret_cast<float*>(base + L.off_rpart);
   d.counter = counter;
   d.stats = out;
   d.u_new = out + 4;
   d.plant_x = c.plant;
+  d.n_normals = normals_per_step(p);
+  d.noise = L.n_normals ? reinterpret_cast<float*>(base + L.off_noise) : nullptr;
   for (uint32_t i = 0; i < p.n_obs; ++i) d.obs[i] = p.obs[i];
 }
 
-uint32_t rollout_block(brmppi_ctx* ctx, int bucket) {
-  if (ctx->forced.block) return ctx->forced.block;
-  return ctx->shape[bucket].block;
+// launch shape of a plain (single-instance) rollout
+LaunchShape plain_shape(brmppi_ctx* ctx, const brmppi_problem& p) {
+  const int bucket = bucket_for(p.n_obs, p.flags);
+  LaunchShape s = ctx->forced.block ? ctx->forced : ctx->shape[bucket_index(bucket)][s_class(p.S)];
+  if (bucket == 0 && s.variant > 1) s.variant = 1;        // unguided: one lane per sample
+  const size_t noise = (size_t)normals_per_step(p) * p.T * round_up(p.S, 256) * sizeof(float);
+  if (variant_pre(s.variant) && noise > kMaxNoiseBytes) s.variant = 0;
+  return s;
+}
+
+ScratchLayout plain_layout(const brmppi_problem& p, const LaunchShape& sh) {
+  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(p) : 0u);
 }
 
 hipEvent_t take_event(brmppi_ctx* ctx) {
@@ -375,11 +407,11 @@ hipEvent_t take_event(brmppi_ctx* ctx) {
   return e;
 }
 
-// launch with optional timing (kind: 0 rollout, 1 weights, 2 reduce, 3 plant)
+// launch with optional timing (kind: 0 rollout, 1 weights, 2 reduce, 3 plant, 4 noise)
 template <typename F>
 int timed(brmppi_ctx* ctx, hipStream_t st, int kind, F&& launch) {
   const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0 ||
-                    ((ctx->flags & BRMPPI_CTX_PROFILE_ROLLOUT) != 0 && kind == 0);
+                    ((ctx->flags & BRMPPI_CTX_PROFILE_ROLLOUT) != 0 && (kind == 0 || kind == 4));
   TimedLaunch tl{kind, nullptr, nullptr};
   if (prof) {
     tl.a = take_event(ctx);
@@ -408,20 +440,26 @@ void collect_timing(brmppi_ctx* ctx) {
   ctx->pending_timing.clear();
 }
 
-// enqueue rollout + weights + reduce of one instance whose descriptor is at d_desc
+// enqueue (noise +) rollout + weights + reduce (+ plant) of one instance whose
+// descriptor is at d_desc, with launch shape sh and scratch layout L
 int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
-                   const ScratchLayout& L) {
+                   const ScratchLayout& L, const LaunchShape& sh) {
   const int bucket = bucket_for(p.n_obs, p.flags);
-  const uint32_t block = rollout_block(ctx, bucket);
-  const uint32_t grid = (p.S + block - 1) / block;
-  int rc = timed(ctx, st, 0, [&] { return launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, st); });
+  const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
+  const uint32_t grid = (p.S + per_tile - 1) / per_tile;
+  int rc;
+  if (variant_pre(sh.variant)) {
+    if (!L.n_normals) return fail(BRMPPI_EINVAL, "internal: noise buffer missing");
+    rc = timed(ctx, st, 4, [&] { return launch_noise(d_desc, p.S, p.T, L.n_normals, st); });
+    if (rc) return rc;
+  }
+  rc = timed(ctx, st, 0, [&] {
+    return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
+  });
   if (rc) return rc;
-  rc = timed(ctx, st, 1, [&] { return launch_weights(d_desc, nullptr, L.n_wchunk, nullptr, L.n_wchunk, st); });
-  if (rc) return rc;
+  // weights, reduction, update, shift and (on request) the plant step
   const uint32_t nr = L.n_wchunk * L.n_rgroup;
-  rc = timed(ctx, st, 2, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
-  if (rc || !(p.flags & BRMPPI_ADVANCE_PLANT)) return rc;
-  return timed(ctx, st, 3, [&] { return launch_plant(d_desc, st); });
+  return timed(ctx, st, 1, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
 }
 
 int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
@@ -441,7 +479,8 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   if (rc) return rc;
   if (!out || !out->u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
   Controller& c = ctx->ctrl[p->controller];
-  const ScratchLayout L = scratch_layout(p->S, p->T);
+  const LaunchShape sh = plain_shape(ctx, *p);
+  const ScratchLayout L = plain_layout(*p, sh);
   // device: [scratch | input block]
   const InputBlock IB = input_block(p->T, p->u_nom != nullptr);
   const size_t in_off = L.bytes;
@@ -462,7 +501,7 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   std::memset(pin + IB.counter, 0, IB.unom - IB.counter);
   if (p->u_nom) std::memcpy(pin + IB.unom, p->u_nom, sizeof(float) * 3 * p->T);
   HIPCHK(hipMemcpyAsync(d_desc, h_desc, IB.bytes, hipMemcpyHostToDevice, s));
-  if ((rc = enqueue_single(ctx, s, d_desc, *p, L))) return rc;
+  if ((rc = enqueue_single(ctx, s, d_desc, *p, L, sh))) return rc;
   HIPCHK(hipMemcpyAsync(pin_out, base + L.off_out, out_floats * sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   collect_timing(ctx);
@@ -491,14 +530,14 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
 struct BatchPlan {
   std::vector<SolveDesc> descs;
   std::vector<Tile> tiles;
-  std::vector<Item> witems, ritems;
+  std::vector<Item> ritems;
   std::vector<ScratchLayout> layouts;
   std::vector<size_t> scratch_off;   // offset of each instance's scratch inside the block
   std::vector<size_t> unom_off;      // offset of each caller nominal sequence (header), or 0
   std::vector<size_t> out_pos;       // float offset of each [stats(4) | u_new(3T)] in the outputs
-  // block layout: header [descs | tiles | witems | ritems | nominals | counters]
+  // block layout: header [descs | tiles | ritems | nominals | counters]
   // (one upload), outputs (one download), then every instance's scratch
-  size_t off_descs = 0, off_tiles = 0, off_witems = 0, off_ritems = 0, off_counters = 0, header_bytes = 0;
+  size_t off_descs = 0, off_tiles = 0, off_ritems = 0, off_counters = 0, header_bytes = 0;
   size_t off_outs = 0, out_floats = 0, total = 0;
   int bucket = 0;
   uint32_t block = 128;
@@ -514,12 +553,12 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
   for (uint32_t i = 0; i < n; ++i) ((ps[i]->flags & BRMPPI_GUIDANCE_OFF) ? any_off : any_on) = true;
   if (any_on && bp.bucket == 0) bp.bucket = 2;
   (void)any_off;
-  bp.block = rollout_block(ctx, bp.bucket);
-  size_t n_tiles = 0, n_w = 0, n_r = 0;
+  // a batch fills the device with samples: one lane per sample, in-kernel noise
+  bp.block = ctx->forced.block ? ctx->forced.block : ctx->batch_block[bucket_index(bp.bucket)];
+  size_t n_tiles = 0, n_r = 0;
   for (uint32_t i = 0; i < n; ++i) {
     bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T);
     n_tiles += (ps[i]->S + bp.block - 1) / bp.block;
-    n_w += bp.layouts[i].n_wchunk;
     n_r += (size_t)bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup;
   }
   size_t o = 0;
@@ -527,8 +566,6 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
   o = round_up(o + sizeof(SolveDesc) * n, 256);
   bp.off_tiles = o;
   o = round_up(o + sizeof(Tile) * n_tiles, 256);
-  bp.off_witems = o;
-  o = round_up(o + sizeof(Item) * n_w, 256);
   bp.off_ritems = o;
   o = round_up(o + sizeof(Item) * n_r, 256);
   // caller-supplied nominal sequences travel with the header
@@ -561,7 +598,6 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
 void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, char* base, BatchPlan& bp) {
   bp.descs.resize(n);
   bp.tiles.clear();
-  bp.witems.clear();
   bp.ritems.clear();
   struct TC {
     double cost;
@@ -578,7 +614,6 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
     // guidance-off instances inside a guided batch: the flag is honoured per tile
     const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + p.n_obs));
     for (uint32_t s0 = 0; s0 < p.S; s0 += bp.block) tc.push_back({cost, Tile{i, s0}});
-    for (uint32_t c = 0; c < bp.layouts[i].n_wchunk; ++c) bp.witems.push_back(Item{i, c});
     for (uint32_t k = 0; k < bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup; ++k) bp.ritems.push_back(Item{i, k});
   }
   // longest tiles first (stable: instance order breaks ties)
@@ -588,39 +623,30 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
 }
 
 uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_tiles) {
-  const int per_cu = rollout_blocks_per_cu(bucket, block);
+  const int per_cu = rollout_blocks_per_cu(bucket, 0, block);
   const size_t g = (size_t)ctx->n_cu * (size_t)std::max(per_cu, 1);
   return (uint32_t)std::max<size_t>(1, std::min(g, n_tiles));
 }
 
+// persistent rollout over the tile list, then the persistent reduce (weights,
+// update, shift, plant steps) over every instance's work items
 int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& bp, BatchCounters* ctr,
                   bool timing) {
   const SolveDesc* descs = reinterpret_cast<const SolveDesc*>(base + bp.off_descs);
   const Tile* tiles = reinterpret_cast<const Tile*>(base + bp.off_tiles);
-  const Item* wi = reinterpret_cast<const Item*>(base + bp.off_witems);
   const Item* ri = reinterpret_cast<const Item*>(base + bp.off_ritems);
-  const uint32_t nt = (uint32_t)bp.tiles.size(), nw = (uint32_t)bp.witems.size(), nr = (uint32_t)bp.ritems.size();
+  const uint32_t nt = (uint32_t)bp.tiles.size(), nr = (uint32_t)bp.ritems.size();
   const uint32_t g_roll = persistent_grid(ctx, bp.bucket, bp.block, nt);
-  const uint32_t g_w = std::max<uint32_t>(1, std::min<uint32_t>(nw, (uint32_t)ctx->n_cu * 8));
   const uint32_t g_r = std::max<uint32_t>(1, std::min<uint32_t>(nr, (uint32_t)ctx->n_cu * 8));
-  auto L0 = [&] { return launch_rollout(bp.bucket, descs, tiles, nt, ctr, g_roll, bp.block, st); };
-  auto L1 = [&] { return launch_weights(descs, wi, nw, ctr, g_w, st); };
-  auto L2 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
-  bool plant = false;
-  for (const SolveDesc& d : bp.descs) plant = plant || (d.flags & BRMPPI_ADVANCE_PLANT);
-  const uint32_t n_inst = (uint32_t)bp.descs.size();
+  auto L0 = [&] { return launch_rollout(bp.bucket, 0, descs, tiles, nt, ctr, g_roll, bp.block, st); };
+  auto L1 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
   int rc;
   if (timing) {
     if ((rc = timed(ctx, st, 0, L0))) return rc;
-    if ((rc = timed(ctx, st, 1, L1))) return rc;
-    if ((rc = timed(ctx, st, 2, L2))) return rc;
-    if (plant) return timed(ctx, st, 3, [&] { return launch_plant_batch(descs, n_inst, st); });
-    return 0;
+    return timed(ctx, st, 1, L1);
   }
   HIPCHK(L0());
   HIPCHK(L1());
-  HIPCHK(L2());
-  if (plant) HIPCHK(launch_plant_batch(descs, n_inst, st));
   return 0;
 }
 
@@ -628,7 +654,6 @@ int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& 
 void stage_batch(const BatchPlan& bp, const brmppi_problem* const* ps, char* pin) {
   std::memcpy(pin + bp.off_descs, bp.descs.data(), sizeof(SolveDesc) * bp.descs.size());
   std::memcpy(pin + bp.off_tiles, bp.tiles.data(), sizeof(Tile) * bp.tiles.size());
-  std::memcpy(pin + bp.off_witems, bp.witems.data(), sizeof(Item) * bp.witems.size());
   std::memcpy(pin + bp.off_ritems, bp.ritems.data(), sizeof(Item) * bp.ritems.size());
   for (size_t i = 0; i < bp.descs.size(); ++i)
     if (ps[i]->u_nom) std::memcpy(pin + bp.unom_off[i], ps[i]->u_nom, sizeof(float) * 3 * ps[i]->T);
@@ -656,7 +681,7 @@ int run_batch(brmppi_ctx* ctx, hipStream_t s, char* base, const BatchPlan& bp, B
     if ((rc = enqueue_batch(ctx, s, base, bp, ctr, true))) return rc;
   } else {
     // the captured launches bake in every pointer and count: key on them
-    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(), bp.witems.size(),
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(),
                                        bp.ritems.size(), (uint64_t)bp.bucket, bp.block,
                                        (uint64_t)(uintptr_t)s, bp.descs.size(), (uint64_t)(uintptr_t)ctr};
     if (key != ctx->graph_key || !ctx->graph_exec) {
@@ -753,7 +778,8 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
     if (!resume) c.plant_set = false;
     return rc;
   }
-  const ScratchLayout L = scratch_layout(p.S, p.T);
+  const LaunchShape sh = plain_shape(ctx, p);
+  const ScratchLayout L = plain_layout(p, sh);
   // device: [scratch | descriptors of every update | counter | nominal | logs];
   // descriptors, counter and nominal sequence travel in one upload
   const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
@@ -793,7 +819,7 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   if (x_out) HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
   for (uint32_t k = 0; k < n_up; ++k) {
     const SolveDesc* dd = reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
-    if ((rc = enqueue_single(ctx, s, dd, p, L))) return rc;   // includes the plant step
+    if ((rc = enqueue_single(ctx, s, dd, p, L, sh))) return rc;   // includes the plant step
     if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
     if (u_applied)
       HIPCHK(hipMemcpyAsync(d_ulog + 3 * k, base + L.off_out + 4 * sizeof(float), sizeof(float) * 3,
@@ -1005,15 +1031,33 @@ int load_tune(brmppi_ctx* ctx) {
   std::stringstream ss;
   ss << f.rdbuf();
   const std::string s = ss.str();
-  // format: {"bucket_<b>": <block>, ...}
-  for (int b : {0, 2, 8, 16, 32}) {
-    const std::string k = "\"bucket_" + std::to_string(b) + "\"";
-    const size_t at = s.find(k);
-    if (at == std::string::npos) continue;
-    const size_t colon = s.find(':', at);
-    if (colon == std::string::npos) continue;
-    const long v = std::strtol(s.c_str() + colon + 1, nullptr, 10);
-    if (v >= 64 && v <= kMaxBlock && v % 64 == 0) ctx->shape[b].block = (uint32_t)v;
+  // format: {"plain_<bucket>_<sclass>": [block, variant], ..., "batch_<bucket>": block}
+  auto valid_block = [](long v) { return v >= 64 && v <= kMaxBlock && v % 64 == 0; };
+  for (int bi = 0; bi < 5; ++bi) {
+    for (int sc = 0; sc < 4; ++sc) {
+      const std::string k = "\"plain_" + std::to_string(kBuckets[bi]) + "_" + std::to_string(sc) + "\"";
+      const size_t at = s.find(k);
+      if (at == std::string::npos) continue;
+      const size_t br = s.find('[', at);
+      if (br == std::string::npos) continue;
+      char* end = nullptr;
+      const long blk = std::strtol(s.c_str() + br + 1, &end, 10);
+      const size_t comma = s.find(',', br);
+      if (comma == std::string::npos) continue;
+      const long var = std::strtol(s.c_str() + comma + 1, nullptr, 10);
+      const int lanes = variant_lanes((int)var);
+      if (valid_block(blk) && var >= 0 && var <= 3 && (kBuckets[bi] > 0 || var <= 1) && blk % (64 * lanes) == 0)
+        ctx->shape[bi][sc] = LaunchShape{(uint32_t)blk, (int)var};
+    }
+    const std::string kb = "\"batch_" + std::to_string(kBuckets[bi]) + "\"";
+    const size_t at = s.find(kb);
+    if (at != std::string::npos) {
+      const size_t colon = s.find(':', at);
+      if (colon != std::string::npos) {
+        const long blk = std::strtol(s.c_str() + colon + 1, nullptr, 10);
+        if (valid_block(blk)) ctx->batch_block[bi] = (uint32_t)blk;
+      }
+    }
   }
   return 0;
 }
@@ -1055,8 +1099,15 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
   int ncu = 0;
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cfg->device));
   ctx->n_cu = ncu > 0 ? ncu : 256;
-  for (auto& s : ctx->shape) s.block = 128;
-  ctx->shape[0].block = 256;
+  // untuned defaults: few samples -> several lanes per sample so that the
+  // launch still covers the device; many samples -> one lane, in-kernel noise
+  for (int bi = 0; bi < 5; ++bi) {
+    const bool guided = kBuckets[bi] > 0;
+    ctx->shape[bi][0] = LaunchShape{256, guided ? 3 : 1};
+    ctx->shape[bi][1] = LaunchShape{256, guided ? 3 : 1};
+    ctx->shape[bi][2] = LaunchShape{256, guided ? 2 : 0};
+    ctx->shape[bi][3] = LaunchShape{128, 0};
+  }
   ctx->ctrl.resize(cfg->max_controllers);
   ctx->counters_blk = ctx->arena.alloc(sizeof(BatchCounters) * 5);
   if (!ctx->counters_blk.ptr) return fail(BRMPPI_ENOMEM, "arena too small");
@@ -1277,16 +1328,18 @@ int brmppi_wait(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st
   }
 }
 
-int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t lanes) {
+int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (block == 0) {
-    ctx->forced = LaunchShape{0, 1};
+    ctx->forced = LaunchShape{0, 0};
+    drop_graph(ctx);
     return BRMPPI_OK;
   }
-  if (block < 64 || block > (uint32_t)kMaxBlock || block % 64) return fail(BRMPPI_EINVAL, "block must be 64..256, multiple of 64");
-  if (lanes != 1) return fail(BRMPPI_EINVAL, "lanes per sample must be 1");
-  ctx->forced = LaunchShape{block, lanes};
+  if (block < 64 || block > (uint32_t)kMaxBlock || block % 64)
+    return fail(BRMPPI_EINVAL, "block must be 64..256, a multiple of 64");
+  if (variant > 3) return fail(BRMPPI_EINVAL, "variant must be 0..3");
+  ctx->forced = LaunchShape{block, (int)variant};
   drop_graph(ctx);
   return BRMPPI_OK;
 }
@@ -1294,9 +1347,10 @@ int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t lanes) {
 int brmppi_autotune(brmppi_ctx* ctx) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  // synthetic problem per bucket: straight path, obstacles around it
-  const uint32_t S = 8192, T = 32;
+  // synthetic problems: straight path, obstacles alternating on both sides
+  const uint32_t T = 16;
   const uint32_t n_path = 400;
+  const uint32_t S_rep[4] = {2048, 8192, 32768, 65536};   // one per S class
   std::vector<float> path(4 * n_path);
   for (uint32_t i = 0; i < n_path; ++i) {
     path[4 * i] = 0.1f * i;
@@ -1304,78 +1358,116 @@ int brmppi_autotune(brmppi_ctx* ctx) {
     path[4 * i + 2] = 0.0f;
     path[4 * i + 3] = 0.0f;
   }
-  const ScratchLayout L = scratch_layout(S, T);
-  const size_t need = L.bytes + round_up(sizeof(SolveDesc), 256) + round_up(sizeof(float4) * n_path, 256) +
-                      round_up(sizeof(float) * 3 * T, 256) + 256;
-  int rc;
-  if ((rc = ensure_scratch(ctx, need))) return rc;
-  char* base = ctx->scratch.ptr;
-  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + L.bytes);
-  float4* d_path = reinterpret_cast<float4*>(base + L.bytes + round_up(sizeof(SolveDesc), 256));
-  float* d_unom = reinterpret_cast<float*>(reinterpret_cast<char*>(d_path) + round_up(sizeof(float4) * n_path, 256));
-  hipStream_t s = ctx->streams[0];
-  HIPCHK(hipMemcpy(d_path, path.data(), sizeof(float4) * n_path, hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(d_unom, 0, sizeof(float) * 3 * T));
   brmppi_params P{};
   P.Ts = 0.05f; P.l1 = 4.0f; P.lh = 0.5f; P.l2 = 10.0f; P.dtheta_max = 0.7f; P.kappa = 0.05f; P.r_disc = 1.0f;
   P.Qc = 2; P.Ql = 2; P.Qth1 = 1; P.Qth2 = 1; P.R_j = 0.05f; P.R_w = 0.05f; P.mu = 0.5f; P.nu_bar = 2;
   P.W_j = 1; P.W_w = 11.1f; P.W_a = 25; P.rho = 0.1f; P.j_lo = -2; P.j_hi = 2; P.w_lo = -0.9f; P.w_hi = 0.9f;
   P.alpha0 = 0.5f; P.alpha_lo = -1; P.alpha_hi = 1; P.sigma_j = 1; P.sigma_w = 0.3f; P.sigma_nu = 0.5f;
   P.sigma_a = 0.2f; P.h_eps = 1e-5f;
-  std::string json = "{";
+  hipStream_t s = ctx->streams[0];
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int bucket : {0, 2, 8, 16, 32}) {
-    SolveDesc h{};
-    std::memset(&h, 0, sizeof(h));
-    h.prm = P;
-    h.lambda = 1.0f;
-    h.inv_lambda = 1.0f;
-    h.x0[2] = 1.0f;
-    h.ds = 0.1f;
-    h.inv_ds = 10.0f;
-    h.S = S;
-    h.T = T;
-    h.n_obs = bucket;
-    h.flags = bucket == 0 ? BRMPPI_GUIDANCE_OFF : 0u;
-    h.n_path = n_path;
-    h.S_pad = L.S_pad;
-    h.n_wchunk = L.n_wchunk;
-    h.n_rgroup = L.n_rgroup;
-    h.n_ritems = L.n_wchunk * L.n_rgroup;
-    h.path = d_path;
-    h.u_nom_in = d_unom;
-    h.u_nom_out = d_unom;
-    h.u_star = reinterpret_cast<float*>(base + L.off_ustar);
-    h.J = reinterpret_cast<float*>(base + L.off_J);
-    for (int o = 0; o < bucket; ++o) {
-      h.obs[o].cx = 2.0f + 1.5f * o;
-      h.obs[o].cy = (o % 2) ? 2.5f : -2.5f;
-      h.obs[o].mx = 0.6f;
-      h.obs[o].my = 0.4f;
-      h.obs[o].heading = 0.3f * o;
-      h.obs[o].e = 2.0f;
-    }
-    HIPCHK(hipMemcpy(d_desc, &h, sizeof(h), hipMemcpyHostToDevice));
-    uint32_t best = ctx->shape[bucket].block;
-    float best_ms = 1e30f;
-    for (uint32_t block : {64u, 128u, 256u}) {
-      const uint32_t grid = (S + block - 1) / block;
-      HIPCHK(launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, s));
-      HIPCHK(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) HIPCHK(launch_rollout(bucket, d_desc, nullptr, grid, nullptr, grid, block, s));
-      HIPCHK(hipEventRecord(e1, s));
-      HIPCHK(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = block;
+  std::string json = "{";
+  auto add = [&](const std::string& k, const std::string& v) {
+    json += std::string(json.size() > 1 ? ", " : "") + "\"" + k + "\": " + v;
+  };
+  int rc = BRMPPI_OK;
+  for (int bi = 0; bi < 5 && rc == BRMPPI_OK; ++bi) {
+    const int bucket = kBuckets[bi];
+    const uint32_t K = bucket == 0 ? 3u : 5u + bucket;
+    for (int sc = 0; sc < 4 && rc == BRMPPI_OK; ++sc) {
+      const uint32_t S = S_rep[sc];
+      const ScratchLayout L = scratch_layout(S, T, K);
+      const size_t off_desc = L.bytes, off_path = off_desc + round_up(sizeof(SolveDesc), 256);
+      const size_t off_unom = off_path + round_up(sizeof(float4) * n_path, 256);
+      const size_t need = off_unom + round_up(sizeof(float) * 3 * T, 256);
+      if (ensure_scratch(ctx, need) != 0) break;   // larger classes do not fit this arena
+      char* base = ctx->scratch.ptr;
+      SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + off_desc);
+      float4* d_path = reinterpret_cast<float4*>(base + off_path);
+      float* d_unom = reinterpret_cast<float*>(base + off_unom);
+      HIPCHK(hipMemcpy(d_path, path.data(), sizeof(float4) * n_path, hipMemcpyHostToDevice));
+      HIPCHK(hipMemset(d_unom, 0, sizeof(float) * 3 * T));
+      SolveDesc h;
+      std::memset(&h, 0, sizeof(h));
+      h.prm = P;
+      h.lambda = 1.0f;
+      h.inv_lambda = 1.0f;
+      h.x0[2] = 1.0f;
+      h.ds = 0.1f;
+      h.inv_ds = 10.0f;
+      h.S = S;
+      h.T = T;
+      h.n_obs = bucket;
+      h.flags = bucket == 0 ? BRMPPI_GUIDANCE_OFF : 0u;
+      h.n_path = n_path;
+      h.S_pad = L.S_pad;
+      h.n_wchunk = L.n_wchunk;
+      h.n_rgroup = L.n_rgroup;
+      h.n_ritems = L.n_wchunk * L.n_rgroup;
+      h.n_normals = K;
+      h.path = d_path;
+      h.u_nom_in = d_unom;
+      h.u_nom_out = d_unom;
+      h.u_star = reinterpret_cast<float*>(base + L.off_ustar);
+      h.J = reinterpret_cast<float*>(base + L.off_J);
+      h.noise = reinterpret_cast<float*>(base + L.off_noise);
+      for (int o = 0; o < bucket; ++o) {
+        h.obs[o].cx = 2.0f + 1.5f * o;
+        h.obs[o].cy = (o % 2) ? 2.5f : -2.5f;
+        h.obs[o].mx = 0.6f;
+        h.obs[o].my = 0.4f;
+        h.obs[o].heading = 0.3f * o;
+        h.obs[o].e = 2.0f;
+      }
+      HIPCHK(hipMemcpy(d_desc, &h, sizeof(h), hipMemcpyHostToDevice));
+      LaunchShape best = ctx->shape[bi][sc];
+      float best_ms = 1e30f, best_v0 = 1e30f;
+      uint32_t best_v0_block = ctx->batch_block[bi];
+      std::string times;             // [block, variant, ms per noise + rollout] of every candidate
+      for (int variant = 0; variant < 4; ++variant) {
+        if (bucket == 0 && variant > 1) continue;
+        const uint32_t lanes = (uint32_t)variant_lanes(variant);
+        for (uint32_t block : {64u, 128u, 256u}) {
+          const uint32_t per_tile = block / lanes;
+          const uint32_t grid = (S + per_tile - 1) / per_tile;
+          auto run = [&]() -> hipError_t {
+            hipError_t e = hipSuccess;
+            if (variant_pre(variant)) e = launch_noise(d_desc, S, T, K, s);
+            if (e == hipSuccess) e = launch_rollout(bucket, variant, d_desc, nullptr, grid, nullptr, grid, block, s);
+            return e;
+          };
+          HIPCHK(run());
+          HIPCHK(hipEventRecord(e0, s));
+          for (int r = 0; r < 3; ++r) HIPCHK(run());
+          HIPCHK(hipEventRecord(e1, s));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          ms /= 3.0f;
+          char buf[64];
+          std::snprintf(buf, sizeof(buf), "%s[%u, %d, %.5f]", times.empty() ? "" : ", ", block, variant, ms);
+          times += buf;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = LaunchShape{block, variant};
+          }
+          if (variant == 0 && sc == 3 && ms < best_v0) {
+            best_v0 = ms;
+            best_v0_block = block;
+          }
+        }
+      }
+      ctx->shape[bi][sc] = best;
+      add("plain_" + std::to_string(bucket) + "_" + std::to_string(sc),
+          "[" + std::to_string(best.block) + ", " + std::to_string(best.variant) + "]");
+      add("ms_plain_" + std::to_string(bucket) + "_" + std::to_string(sc), "[" + times + "]");
+      if (sc == 3) {
+        ctx->batch_block[bi] = best_v0_block;
+        add("batch_" + std::to_string(bucket), std::to_string(best_v0_block));
       }
     }
-    ctx->shape[bucket].block = best;
-    json += std::string(json.size() > 1 ? ", " : "") + "\"bucket_" + std::to_string(bucket) + "\": " + std::to_string(best);
   }
   json += "}\n";
   (void)hipEventDestroy(e0);
@@ -1385,15 +1477,16 @@ int brmppi_autotune(brmppi_ctx* ctx) {
     std::ofstream f(ctx->tune_path);
     if (f) f << json;
   }
-  return BRMPPI_OK;
+  return rc;
 }
 
-int brmppi_profile_read(brmppi_ctx* ctx, double out[8]) {
+int brmppi_profile_read(brmppi_ctx* ctx, double out[6]) {
   if (!ctx || !out) return fail(BRMPPI_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  for (int k = 0; k < 4; ++k) {
-    out[2 * k] = ctx->prof.ms[k];
-    out[2 * k + 1] = ctx->prof.n[k];
+  const int kinds[3] = {0, 1, 4};   // rollout, reduce, noise
+  for (int k = 0; k < 3; ++k) {
+    out[2 * k] = ctx->prof.ms[kinds[k]];
+    out[2 * k + 1] = ctx->prof.n[kinds[k]];
   }
   return BRMPPI_OK;
 }

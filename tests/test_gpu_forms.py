@@ -162,16 +162,54 @@ def test_closed_loop_matches_plain_and_oracle_plant(ctx):
         assert np.allclose(x_cl[k + 1], want, rtol=1e-14, atol=1e-14), k
 
 
-def test_autotune_keeps_results(ctx, tmp_path):
-    p = W.random_small(80, S=3000, T=12, n_obs=7)
+@pytest.mark.parametrize("n_obs,flags", [(7, 0), (2, 0), (13, W.FLAG_HITCH_OFF), (29, 0), (5, W.FLAG_GUIDANCE_OFF)])
+def test_launch_shapes_bitwise_identical(ctx, n_obs, flags):
+    """every (block size, lanes per sample, noise source) gives the same bits:
+    costs, applied sequences and the update"""
+    p = W.random_small(80 + n_obs, S=2999, T=12, n_obs=n_obs).copy(flags=flags)
+    ctx.set_path(406, p.path, p.ds)
+    B.brmppi_set_launch(ctx.h, 64, 0)
+    ref = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=406), want_J=True, want_useq=True)
+    for variant in (0, 1, 2, 3):
+        if flags & W.FLAG_GUIDANCE_OFF and variant > 1:
+            continue
+        for block in (64, 128, 256):
+            log(f"  shape block={block} variant={variant} n_obs={n_obs}")
+            B.brmppi_set_launch(ctx.h, block, variant)
+            g = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=406), want_J=True, want_useq=True)
+            assert np.array_equal(g["J"], ref["J"]), (block, variant)
+            assert np.array_equal(g["useq"], ref["useq"]), (block, variant)
+            assert np.array_equal(g["U_new"], ref["U_new"]), (block, variant)
+    B.brmppi_set_launch(ctx.h, 0, 0)
+
+
+def test_default_launch_table_in_effect():
+    """a fresh context uses its launch table (no shape forced): a guided solve
+    with S <= 8192 runs four lanes per sample with the separate noise kernel,
+    an unguided one a single lane"""
+    c = B.Context(arena_bytes=1 << 30, n_streams=1, max_controllers=4, flags_extra=B.CTX_PROFILE_ROLLOUT)
+    try:
+        p = W.random_small(91, S=3000, T=12, n_obs=7)
+        c.set_path(0, p.path, p.ds)
+        B.brmppi_solve(c.h, B.ProblemBuffers(p, controller=0))
+        prof = B.brmppi_profile_read(c.h)
+        assert prof["rollout"]["count"] == 1 and prof["noise"]["count"] == 1
+        B.brmppi_profile_reset(c.h)
+        B.brmppi_set_launch(c.h, 128, 0)
+        B.brmppi_solve(c.h, B.ProblemBuffers(p, controller=0))
+        prof = B.brmppi_profile_read(c.h)
+        assert prof["rollout"]["count"] == 1 and prof["noise"]["count"] == 0
+    finally:
+        c.close()
+
+
+def test_autotune(ctx, tmp_path):
+    p = W.random_small(90, S=3000, T=12, n_obs=7)
     ctx.set_path(406, p.path, p.ds)
     before = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=406))[0]
     B.brmppi_autotune(ctx.h)
-    for block in (64, 128, 256):
-        B.brmppi_set_launch(ctx.h, block, 1)
-        after = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=406))[0]
-        assert np.array_equal(before, after), block
-    B.brmppi_set_launch(ctx.h, 0, 1)
+    after = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=406))[0]
+    assert np.array_equal(before, after)
 
 
 def test_invalid_arguments_leave_state(ctx):
