@@ -220,9 +220,11 @@ int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_upda
 int brmppi_autotune(brmppi_ctx* ctx);
 /* Force a rollout launch shape for every plain and batched launch: block size
  * 64..256 (multiple of 64) and variant 0 = one lane per sample, noise drawn in
- * the kernel; 1 = one lane, noise from the parallel kernel; 2 / 3 = two / four
- * lanes per sample, noise from the parallel kernel (batched launches always
- * use variant 0).  block 0 restores the tuned/default choice. */
+ * the kernel; 1 = one lane, noise from the parallel kernel; 2 / 3 / 4 = two /
+ * four / eight lanes per sample, noise from the parallel kernel (batched
+ * launches always use variant 0; an instance without guidance runs variant
+ * 0 or 1).  block 0 restores the tuned/default choice.  EINVAL for a block
+ * outside 64..256 or not a multiple of 64, or a variant above 4. */
 int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant);
 /* Kernel timings accumulated under BRMPPI_CTX_PROFILE (ms totals and counts):
  * out[0..1] rollout, out[2..3] reduce (weights + average + shift + plant),

@@ -282,7 +282,7 @@ def brmppi_autotune(ctx):
 
 def brmppi_set_launch(ctx, block, variant=0):
     """variant: 0 one lane per sample (in-kernel noise), 1 one lane (noise kernel),
-    2 / 3 two / four lanes per sample (noise kernel); block 0 = tuned default"""
+    2 / 3 / 4 two / four / eight lanes per sample (noise kernel); block 0 = tuned default"""
     return check(lib().brmppi_set_launch(ctx, int(block), int(variant)))
 
 

@@ -55,6 +55,7 @@ struct alignas(16) BatchCounters {
 // with precomputed noise, 2 / 3 = two / four lanes per sample with
 // precomputed noise (k_noise must run first).  All variants give bitwise
 // identical results.
+constexpr int kMaxVariant = 4;   // 0: G1 fused noise, 1: G1, 2: G2, 3: G4, 4: G8 (precomputed noise)
 int variant_lanes(int variant);
 bool variant_pre(int variant);
 hipError_t launch_rollout(int bucket, int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,

@@ -22,6 +22,8 @@
 // far from the origin.
 #include <math.h>
 
+#include <type_traits>
+
 #include "brmppi_internal.h"
 
 namespace brm {
@@ -178,18 +180,25 @@ __device__ __forceinline__ RowTerms row_terms(const ProjConst& K, float hhat, fl
   return R;
 }
 
-// 2x2 normal equations of the eliminated projection, accumulated in FP64
-struct Normal2 {
+// Row sums of the 2x2 normal equations of the eliminated projection,
+// accumulated in FP64: sum_i c_i g_i g_i' and sum_i c_i g_i rr_i
+struct Acc5 {
   double N00, N01, N11, y0, y1;
 };
 
-__device__ __forceinline__ void accumulate(Normal2& A, float c, float g0, float g1, float rr) {
-  const double cg0 = (double)c * (double)g0, cg1 = (double)c * (double)g1;
-  A.N00 = fma(cg0, (double)g0, A.N00);
-  A.N01 = fma(cg0, (double)g1, A.N01);
-  A.N11 = fma(cg1, (double)g1, A.N11);
-  A.y0 = fma(cg0, (double)rr, A.y0);
-  A.y1 = fma(cg1, (double)rr, A.y1);
+__device__ __forceinline__ Acc5 acc_zero() { return Acc5{0.0, 0.0, 0.0, 0.0, 0.0}; }
+
+__device__ __forceinline__ void acc_row(Acc5& A, const RowTerms& R) {
+  const double cg0 = (double)R.c * (double)R.g0, cg1 = (double)R.c * (double)R.g1;
+  A.N00 = fma(cg0, (double)R.g0, A.N00);
+  A.N01 = fma(cg0, (double)R.g1, A.N01);
+  A.N11 = fma(cg1, (double)R.g1, A.N11);
+  A.y0 = fma(cg0, (double)R.rr, A.y0);
+  A.y1 = fma(cg1, (double)R.rr, A.y1);
+}
+
+__device__ __forceinline__ Acc5 acc_add(const Acc5& a, const Acc5& b) {
+  return Acc5{a.N00 + b.N00, a.N01 + b.N01, a.N11 + b.N11, a.y0 + b.y0, a.y1 + b.y1};
 }
 
 // obstacle row, eqs. (16)-(17) with e = 2: with q = d + Ts d_dot,
@@ -225,25 +234,62 @@ __device__ __forceinline__ ObsRow obstacle_row(const ObsL& ob, float px, float p
 }
 
 // value held by lane Q of each G-lane group, broadcast to the group (DPP quad
-// permute; G divides 4 so a group never crosses a quad)
+// permute; G = 2 or 4 divides a quad, G = 8 groups hold two quads that each
+// carry the value)
 template <int G, int Q>
 __device__ __forceinline__ float group_bcast(float x) {
   if constexpr (G == 1) {
     return x;
   } else {
-    constexpr int ctrl = (G == 4) ? (Q * 0x55) : ((Q) | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6));
+    constexpr int ctrl = (G >= 4) ? (Q * 0x55) : ((Q) | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6));
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), ctrl, 0xF, 0xF, false));
   }
 }
 
+// DPP controls of the three butterfly levels over 8 lanes: lane i reads lane
+// i ^ 1, i ^ 2 (quad permutes), then 7 - i (half-row mirror: the other quad)
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+
+template <int CTRL>
+__device__ __forceinline__ Acc5 acc_partner_add(const Acc5& a) {
+  return acc_add(a, Acc5{dpp_f64<CTRL>(a.N00), dpp_f64<CTRL>(a.N01), dpp_f64<CTRL>(a.N11), dpp_f64<CTRL>(a.y0),
+                         dpp_f64<CTRL>(a.y1)});
+}
+
+// Canonical accumulation order of the projection rows, independent of the
+// number G of lanes per sample: row r belongs to virtual lane v(r) (hitch row
+// k -> v = k, obstacle o -> v = o mod 8); a virtual lane sums its rows from
+// zero in row order (hitch row first, then obstacles v, v + 8, ...); the 8
+// virtual sums are added by a fixed binary tree (v ^ 1, then v ^ 2, then v ^ 4).
+// Lane q of a group owns virtual lanes q + G i.  The levels that pair virtual
+// lanes on different lanes run as DPP butterflies (IEEE addition commutes, so
+// both partners hold the same bits), the rest inside the lane.
 template <int G>
-__device__ __forceinline__ float group_bcast_dyn(float x, int q) {
-  // q is a compile-time constant at every call site after unrolling
-  switch (q) {
-    case 0: return group_bcast<G, 0>(x);
-    case 1: return group_bcast<G, (G > 1 ? 1 : 0)>(x);
-    case 2: return group_bcast<G, (G > 2 ? 2 : 0)>(x);
-    default: return group_bcast<G, (G > 3 ? 3 : 0)>(x);
+__device__ __forceinline__ Acc5 cross_lane_levels(Acc5 a) {
+  if constexpr (G >= 2) a = acc_partner_add<kDppXor1>(a);
+  if constexpr (G >= 4) a = acc_partner_add<kDppXor2>(a);
+  if constexpr (G >= 8) a = acc_partner_add<kDppHalfMirror>(a);
+  return a;
+}
+
+template <int G, int LO, int N, typename Leaf>
+__device__ __forceinline__ Acc5 virtual_tree(Leaf& leaf) {
+  if constexpr (N == 1) {
+    return cross_lane_levels<G>(leaf(std::integral_constant<int, LO>{}));
+  } else {
+    const Acc5 l = virtual_tree<G, LO, N / 2>(leaf);
+    const Acc5 r = virtual_tree<G, LO + N / 2, N / 2>(leaf);
+    return acc_add(l, r);
   }
 }
 
@@ -252,13 +298,75 @@ __device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t t
   return d.noise + ((size_t)tau * d.n_normals + k) * d.S_pad;
 }
 
+// sine and cosine of the four angles a step needs (th1, th1 - th2, delta and
+// the reference heading), one sincos per lane for G >= 4, then broadcast
+struct StepTrig {
+  float s1, c1, sp, cp, sd, cd, sr, cr;
+};
+
+template <int G>
+__device__ __forceinline__ StepTrig step_trig(int g, float a0, float a1, float a2, float a3) {
+  StepTrig t;
+  if constexpr (G == 1) {
+    sincosf(a0, &t.s1, &t.c1);
+    sincosf(a1, &t.sp, &t.cp);
+    sincosf(a2, &t.sd, &t.cd);
+    sincosf(a3, &t.sr, &t.cr);
+  } else if constexpr (G == 2) {
+    // lane g: angles g and g + 2
+    float s0, c0, s2, c2;
+    sincosf(g == 0 ? a0 : a1, &s0, &c0);
+    sincosf(g == 0 ? a2 : a3, &s2, &c2);
+    t.s1 = group_bcast<2, 0>(s0);
+    t.c1 = group_bcast<2, 0>(c0);
+    t.sp = group_bcast<2, 1>(s0);
+    t.cp = group_bcast<2, 1>(c0);
+    t.sd = group_bcast<2, 0>(s2);
+    t.cd = group_bcast<2, 0>(c2);
+    t.sr = group_bcast<2, 1>(s2);
+    t.cr = group_bcast<2, 1>(c2);
+  } else {
+    // lane g of every quad: angle g mod 4
+    const int k = g & 3;
+    const float a = k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
+    float sa, ca;
+    sincosf(a, &sa, &ca);
+    t.s1 = group_bcast<G, 0>(sa);
+    t.c1 = group_bcast<G, 0>(ca);
+    t.sp = group_bcast<G, 1>(sa);
+    t.cp = group_bcast<G, 1>(ca);
+    t.sd = group_bcast<G, 2>(sa);
+    t.cd = group_bcast<G, 2>(ca);
+    t.sr = group_bcast<G, 3>(sa);
+    t.cr = group_bcast<G, 3>(ca);
+  }
+  return t;
+}
+
+// Tracking part of eq. (13) with the reference heading's sine and cosine given.
+__device__ __forceinline__ float tracking_cost_sc(const brmppi_params& P, const RefPoint& rf, float sr, float cr,
+                                                  float px, float py, float th1, float th2) {
+  const float ex = px - rf.x, ey = py - rf.y;
+  const float ec = sr * ex - cr * ey;
+  const float el = -cr * ex - sr * ey;
+  const float e1 = wrap_angle(th1 - rf.th1);
+  const float e2 = wrap_angle(th2 - rf.th2);
+  return P.Qc * ec * ec + P.Ql * el * el + P.Qth1 * e1 * e1 + P.Qth2 * e2 * e2;
+}
+
+// One sample's rollout over T steps, run by the G lanes of its group (lane g).
+// Rows: every lane computes the hitch row g mod 2 (G = 1: both), obstacle o is
+// computed by lane o mod G in its slot o / G.  After the projection every lane
+// holds the same inputs, state and cost.
 template <int NOB, bool GUIDED, int G, bool PRE>
 __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
                                                int w0, int nw, int k0, float phi0) {
-  static_assert(G == 1 || G == 2 || G == 4, "lanes per sample");
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per sample");
   static_assert(PRE || G == 1, "a sample shared by lanes reads precomputed normals");
   constexpr int NSL = GUIDED ? (NOB + G - 1) / G : 1;   // obstacle slots of this lane
+  constexpr int NV = 8 / G;                            // virtual lanes of this lane
+  constexpr int NH = (G == 1) ? 2 : 1;                 // hitch rows computed by this lane
   constexpr int NBMAX = GUIDED ? (5 + NOB + 3) / 4 : 1;  // Philox blocks (fused noise)
   const brmppi_params& P = d.prm;
   const float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
@@ -271,6 +379,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const float ox = x0[0], oy = x0[1];
   const float4* __restrict__ gpath = d.path;
   const int n_path = (int)d.n_path;
+  const int hk0 = (G == 1) ? 0 : (g & 1);    // first hitch row of this lane
 
   // soft-bound projection constants, eq. (11): M = W + rho I,
   // p = W z_des + rho/2 (lo + hi)
@@ -286,7 +395,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const float pw0 = 0.5f * P.rho * (P.w_lo + P.w_hi);
 
   float px = 0.0f, py = 0.0f, v = x0[2], a = x0[3], th1 = x0[4], th2 = x0[5], dl = x0[6], psi = 0.0f;
-  float alpha_h[2] = {P.alpha0, P.alpha0};
+  float alpha_h[NH];
+#pragma unroll
+  for (int k = 0; k < NH; ++k) alpha_h[k] = P.alpha0;
   float alpha_o[NSL];
 #pragma unroll
   for (int j = 0; j < NSL; ++j) alpha_o[j] = P.alpha0;
@@ -296,14 +407,14 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const float* __restrict__ unom = d.u_nom_in;
 
   // precomputed normals of the next step (prefetched one step ahead)
-  float nx_in[3], nx_h[2], nx_o[NSL];
+  float nx_in[3], nx_h[NH], nx_o[NSL];
   auto load_normals = [&](uint32_t tau) {
     if constexpr (PRE) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) nx_in[k] = noise_row(d, tau, k)[s];
       if (guided) {
-        nx_h[0] = noise_row(d, tau, 3)[s];
-        nx_h[1] = noise_row(d, tau, 4)[s];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) nx_h[k] = noise_row(d, tau, 3 + hk0 + k)[s];
 #pragma unroll
         for (int j = 0; j < NSL; ++j) {
           const int o = g + G * j;
@@ -317,12 +428,12 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   for (uint32_t tau = 0; tau < d.T; ++tau) {
     // --- noise: normals 0..2 perturb the inputs, 3 and 4 the hitch rows'
     // auxiliary inputs, 5 + o obstacle o's ---
-    float e_in[3], e_h[2], e_o[NSL];
+    float e_in[3], e_h[NH], e_o[NSL];
     if constexpr (PRE) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) e_in[k] = nx_in[k];
-      e_h[0] = nx_h[0];
-      e_h[1] = nx_h[1];
+#pragma unroll
+      for (int k = 0; k < NH; ++k) e_h[k] = nx_h[k];
 #pragma unroll
       for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[j];
       if (tau + 1 < d.T) load_normals(tau + 1);
@@ -339,8 +450,8 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 #pragma unroll
       for (int k = 0; k < 3; ++k) e_in[k] = eps[k];
       if constexpr (GUIDED) {
-        e_h[0] = eps[3];
-        e_h[1] = eps[4];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) e_h[k] = eps[3 + k];
 #pragma unroll
         for (int j = 0; j < NSL; ++j) e_o[j] = eps[5 + j];   // G == 1: slot j is obstacle j
       }
@@ -349,10 +460,10 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     float uw = unom[3 * tau + 1] + P.sigma_w * e_in[1];
     const float unu = unom[3 * tau + 2] + P.sigma_nu * e_in[2];
 
-    float s1, c1, sp, cp;
-    sincosf(th1, &s1, &c1);
-    sincosf(th1 - th2, &sp, &cp);
-    const float tn = tanf(dl);
+    const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+    const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
+    const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
+    const float tn = tg.sd / tg.cd;
     const float kd = tn * inv_l1;     // th1_dot = v kd
     const float vkd = v * kd;
     const float Aw2 = sp - ch * cp * tn;
@@ -360,16 +471,10 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     if (GUIDED && guided) {
       const float sec2 = 1.0f + tn * tn;
       const float t = d.t0 + (float)tau * Ts;
-      Normal2 A;
-      A.N00 = Mj;
-      A.N01 = 0.0;
-      A.N11 = Mw;
-      A.y0 = (double)(P.W_j * uj + pj0);
-      A.y1 = (double)(P.W_w * uw + pw0);
 
       // hitch rows, eq. (18) split into h_s = dth_max - kappa v + s (th1 - th2),
-      // first-order expansion hhat = h + Ts hd (every lane computes both)
-      RowTerms H[2];
+      // first-order expansion hhat = h + Ts hd
+      RowTerms H[NH];
       if (hitch) {
         const float D = v * inv_l2 * Aw2 - vkd;                 // th2_dot - th1_dot
         const float D_v = inv_l2 * Aw2 - kd;
@@ -377,60 +482,57 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
         const float D_dl = -v * sec2 * (inv_l2 * ch * cp + inv_l1);
         const float phi = th1 - th2;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const float sg = k == 0 ? 1.0f : -1.0f;
+        for (int k = 0; k < NH; ++k) {
+          const float sg = (hk0 + k) == 0 ? 1.0f : -1.0f;
           const float h = P.dtheta_max - P.kappa * v + sg * phi;
           const float hd = -P.kappa * a - sg * D;
           const float hv = -P.kappa - sg * Ts * D_v;
           const float Lf = Ts * (hv * a - sg * (1.0f - Ts * D_phi) * D);
           H[k] = row_terms(K, h + Ts * hd, Lf, -P.kappa * Ts2, -sg * Ts2 * D_dl, P.sigma_a * e_h[k], alpha_h[k]);
-          accumulate(A, H[k].c, H[k].g0, H[k].g1, H[k].rr);
         }
       }
-      // obstacle rows of this lane's slots
+      // rows of virtual lane g + G i: its hitch row, then obstacles in order
       RowTerms O[NSL];
+      auto leaf = [&](auto I) -> Acc5 {
+        constexpr int i = decltype(I)::value;
+        const int vl = g + G * i;
+        Acc5 A = acc_zero();
+        if (hitch && vl < 2) acc_row(A, H[(G == 1) ? vl : 0]);
 #pragma unroll
-      for (int j = 0; j < NSL; ++j) {
-        const int o = (G == 1) ? j : g + G * j;
-        if (o < n_obs) {
-          const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
-          O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
-        } else {
-          O[j].c = O[j].g0 = O[j].g1 = O[j].rr = O[j].Lf = O[j].ih = 0.0f;
+        for (int j = i; j < NSL; j += NV) {
+          const int o = g + G * j;
+          if (o < n_obs) {
+            const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+            O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+            acc_row(A, O[j]);
+          }
         }
-      }
-      // every lane accumulates every obstacle row in obstacle order
-#pragma unroll
-      for (int o = 0; o < NOB; ++o) {
-        if (o < n_obs) {
-          const int j = o / G, q = o % G;
-          accumulate(A, group_bcast_dyn<G>(O[j].c, q), group_bcast_dyn<G>(O[j].g0, q),
-                     group_bcast_dyn<G>(O[j].g1, q), group_bcast_dyn<G>(O[j].rr, q));
-        }
-      }
-      const double det = A.N00 * A.N11 - A.N01 * A.N01;
+        return A;
+      };
+      const Acc5 S8 = virtual_tree<G, 0, NV>(leaf);
+      const double N00 = (double)Mj + S8.N00, N01 = S8.N01, N11 = (double)Mw + S8.N11;
+      const double y0 = (double)(P.W_j * uj + pj0) + S8.y0;
+      const double y1 = (double)(P.W_w * uw + pw0) + S8.y1;
+      const double det = N00 * N11 - N01 * N01;
       const double idet = 1.0 / det;
-      const double u0 = (A.N11 * A.y0 - A.N01 * A.y1) * idet;
-      const double u1 = (A.N00 * A.y1 - A.N01 * A.y0) * idet;
-      uj = (float)u0;
-      uw = (float)u1;
+      uj = (float)((N11 * y0 - N01 * y1) * idet);
+      uw = (float)((N00 * y1 - N01 * y0) * idet);
       // next barrier rates: alpha + u*alpha = -(Lf + g u*)/hh (eq. (9) holds exactly)
       if (hitch) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) alpha_h[k] = -(H[k].Lf + H[k].g0 * uj + H[k].g1 * uw) * H[k].ih;
+        for (int k = 0; k < NH; ++k) alpha_h[k] = -(H[k].Lf + H[k].g0 * uj + H[k].g1 * uw) * H[k].ih;
       }
 #pragma unroll
       for (int j = 0; j < NSL; ++j) {
-        const int o = (G == 1) ? j : g + G * j;
+        const int o = g + G * j;
         if (o < n_obs) alpha_o[j] = -(O[j].Lf + O[j].g0 * uj + O[j].g1 * uw) * O[j].ih;
       }
     }
 
     // --- stage cost r(x_tau, u*_tau, psi_tau), eq. (13) ---
-    const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     const float prog = P.nu_bar - unu;
-    const float rc = tracking_cost(P, rf, px, py, th1, th2) + P.R_j * uj * uj + P.R_w * uw * uw +
-                     P.mu * prog * prog;
+    const float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
+                     P.R_w * uw * uw + P.mu * prog * prog;
     J += (double)rc;
 
     // --- applied inputs [3T][S_pad] ---
@@ -701,6 +803,13 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
   const uint32_t nW = d.n_wchunk;
   const uint32_t R = 3 * d.T;
   const uint32_t nt = blockDim.x;
+  // the first 8 chunk partials of this thread's first row, loaded before the
+  // merge's barriers so that their latency overlaps them
+  constexpr int kPre = 8;
+  const uint32_t r0 = threadIdx.x;
+  float pre[kPre];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? d.rpart[(size_t)k * R + r0] : 0.0f;
   float mloc = INFINITY;
   for (uint32_t c = threadIdx.x; c < nW; c += nt) {
     mloc = fminf(mloc, d.wpart[c].x);
@@ -723,14 +832,21 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
       const float* __restrict__ col = d.rpart + r;
       float acc = 0.0f;
       uint32_t c = 0;
-      for (; c + 8 <= nW; c += 8) {
-        float v[8];
+      for (; c + kPre <= nW; c += kPre) {
+        const bool use_pre = (c == 0) && (r == r0);
+        float v[kPre];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = col[(size_t)(c + k) * R];
+        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : col[(size_t)(c + k) * R];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc += s_scale[c + k] * v[k];
+        for (int k = 0; k < kPre; ++k) acc += s_scale[c + k] * v[k];
       }
-      for (; c < nW; ++c) acc += s_scale[c] * col[(size_t)c * R];
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) {
+        if (c + k < nW) {
+          const float vk = (c == 0 && r == r0) ? pre[k] : col[(size_t)(c + k) * R];
+          acc += s_scale[c + k] * vk;
+        }
+      }
       const float U = acc * iZ;
       d.u_new[r] = U;
       // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
@@ -781,6 +897,18 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     const uint32_t base = chunk * kWChunk;
     const uint32_t R = 3 * d.T;
     const uint32_t S = d.S;
+
+    // this wave's row of the chunk is loaded first so that its latency
+    // overlaps the costs' load and the weights
+    const uint32_t r = rg * kRowsPerBlock + wid;
+    constexpr int kRowLoads = kWChunk / 4 / 64;
+    float4 urow[kRowLoads];
+#pragma unroll
+    for (int k = 0; k < kRowLoads; ++k) {
+      const uint32_t s = base + 4 * (lane + 64 * k);
+      urow[k] = (r < R && s < d.S_pad) ? *reinterpret_cast<const float4*>(d.u_star + (size_t)r * d.S_pad + s)
+                                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 
     // --- the chunk's weights (thread t: samples base + 4t .. base + 4t + 3) ---
     const uint32_t s4 = base + 4 * threadIdx.x;
@@ -833,23 +961,19 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     }
 
     // --- one wave per row: sum_s gamma_s u*[r][s] over the chunk ---
-    const uint32_t r = rg * kRowsPerBlock + wid;
     if (r < R) {
-      const float* __restrict__ row = d.u_star + (size_t)r * d.S_pad;
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k < kWChunk / 4 / 64; ++k) {
+      for (int k = 0; k < kRowLoads; ++k) {
         const uint32_t i4 = lane + 64 * k;
         const uint32_t s = base + 4 * i4;
-        if (s < d.S_pad) {
-          const float4 u = *reinterpret_cast<const float4*>(row + s);
-          const float4 w = s_gam[i4];
-          // samples past S hold no data: select, never multiply
-          acc += (s + 0 < S) ? w.x * u.x : 0.0f;
-          acc += (s + 1 < S) ? w.y * u.y : 0.0f;
-          acc += (s + 2 < S) ? w.z * u.z : 0.0f;
-          acc += (s + 3 < S) ? w.w * u.w : 0.0f;
-        }
+        const float4 u = urow[k];
+        const float4 w = s_gam[i4];
+        // samples past S hold no data: select, never multiply
+        acc += (s + 0 < S) ? w.x * u.x : 0.0f;
+        acc += (s + 1 < S) ? w.y * u.y : 0.0f;
+        acc += (s + 2 < S) ? w.z * u.z : 0.0f;
+        acc += (s + 3 < S) ? w.w * u.w : 0.0f;
       }
       acc = wave_sum(acc);
       if (lane == 0) d.rpart[(size_t)chunk * R + r] = acc;
@@ -909,8 +1033,9 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t n) {
 // launchers
 // ---------------------------------------------------------------------------
 // rollout variants: 0 = one lane per sample, in-kernel noise; 1 = one lane,
-// precomputed noise; 2 / 3 = two / four lanes per sample, precomputed noise
-int variant_lanes(int variant) { return variant == 2 ? 2 : (variant == 3 ? 4 : 1); }
+// precomputed noise; 2 / 3 / 4 = two / four / eight lanes per sample,
+// precomputed noise
+int variant_lanes(int variant) { return variant == 2 ? 2 : (variant == 3 ? 4 : (variant == 4 ? 8 : 1)); }
 bool variant_pre(int variant) { return variant != 0; }
 
 template <int NOB, bool GD, int G, bool PRE>
@@ -931,6 +1056,9 @@ static hipError_t launch_variant(int variant, const SolveDesc* descs, const Tile
       return hipErrorInvalidValue;
     case 3:
       if constexpr (GD) return launch_rollout_t<NOB, GD, 4, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      return hipErrorInvalidValue;
+    case 4:
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 8, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -966,6 +1094,9 @@ static int occ_variant(int variant, uint32_t block) {
       return 1;
     case 3:
       if constexpr (GD) return occ_t<NOB, GD, 4, true>(block);
+      return 1;
+    case 4:
+      if constexpr (GD) return occ_t<NOB, GD, 8, true>(block);
       return 1;
     default: return occ_t<NOB, GD, 1, false>(block);
   }

@@ -274,6 +274,10 @@ struct brmppi_ctx {
   Profile prof;
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> pending_timing;
+  // closed loop: noise of update k + 1 on a second stream during update k
+  // (events: noise ready / rollout done, per buffer parity)
+  hipEvent_t cl_noise[2] = {nullptr, nullptr};
+  hipEvent_t cl_roll[2] = {nullptr, nullptr};
 
   // served form
   std::mutex mu;                // guards everything below and every device enqueue
@@ -442,6 +446,28 @@ void collect_timing(brmppi_ctx* ctx) {
 
 // enqueue (noise +) rollout + weights + reduce (+ plant) of one instance whose
 // descriptor is at d_desc, with launch shape sh and scratch layout L
+int enqueue_noise(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
+                  const ScratchLayout& L) {
+  if (!L.n_normals) return fail(BRMPPI_EINVAL, "internal: noise buffer missing");
+  return timed(ctx, st, 4, [&] { return launch_noise(d_desc, p.S, p.T, L.n_normals, st); });
+}
+
+// rollout + weights + reduce (+ plant) of one instance whose normals, if the
+// shape reads them, are already in its noise buffer (or ordered before on st)
+int enqueue_rollout_reduce(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
+                           const ScratchLayout& L, const LaunchShape& sh, hipEvent_t after_rollout) {
+  const int bucket = bucket_for(p.n_obs, p.flags);
+  const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
+  const uint32_t grid = (p.S + per_tile - 1) / per_tile;
+  int rc = timed(ctx, st, 0, [&] {
+    return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
+  });
+  if (rc) return rc;
+  if (after_rollout) HIPCHK(hipEventRecord(after_rollout, st));
+  const uint32_t nr = L.n_wchunk * L.n_rgroup;
+  return timed(ctx, st, 1, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
+}
+
 int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
                    const ScratchLayout& L, const LaunchShape& sh) {
   const int bucket = bucket_for(p.n_obs, p.flags);
@@ -449,9 +475,7 @@ int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, con
   const uint32_t grid = (p.S + per_tile - 1) / per_tile;
   int rc;
   if (variant_pre(sh.variant)) {
-    if (!L.n_normals) return fail(BRMPPI_EINVAL, "internal: noise buffer missing");
-    rc = timed(ctx, st, 4, [&] { return launch_noise(d_desc, p.S, p.T, L.n_normals, st); });
-    if (rc) return rc;
+    if ((rc = enqueue_noise(ctx, st, d_desc, p, L))) return rc;
   }
   rc = timed(ctx, st, 0, [&] {
     return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
@@ -788,8 +812,14 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   const size_t unom_rel = ctr_rel + 256;
   const size_t in_bytes = unom_rel + (p.u_nom ? sizeof(float) * 3 * p.T : 0);
   const size_t log_off = in_off + round_up(in_bytes, 256);
-  const size_t need = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
-                      round_up(sizeof(float) * 3 * n_up, 256);
+  const size_t log_end = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
+                         round_up(sizeof(float) * 3 * n_up, 256);
+  // the normals of update k + 1 are drawn on a second stream while update k
+  // runs: odd updates read a second noise buffer
+  const bool overlap = variant_pre(sh.variant) && ctx->n_streams >= 2 && n_up > 1;
+  const size_t noise_bytes = (size_t)L.n_normals * p.T * L.S_pad * sizeof(float);
+  const size_t noise2_off = log_end;
+  const size_t need = log_end + (overlap ? round_up(noise_bytes, 256) : 0);
   if ((rc = ensure_scratch(ctx, need))) return rc;
   char* base = ctx->scratch.ptr;
   hipStream_t s = ctx->streams[0];
@@ -806,6 +836,7 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
     SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
     // only the first update reads the caller's sequence; later ones the shifted result
     fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out);
+    if (overlap && (k & 1)) hd->noise = reinterpret_cast<float*>(base + noise2_off);
   }
   std::memset(pin + ctr_rel, 0, 256);
   if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, sizeof(float) * 3 * p.T);
@@ -817,9 +848,34 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   }
   HIPCHK(hipMemcpyAsync(base + in_off, pin, in_bytes, hipMemcpyHostToDevice, s));
   if (x_out) HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+  hipStream_t side = ctx->streams[1];
+  if (overlap) {
+    for (int b = 0; b < 2; ++b) {
+      if (!ctx->cl_noise[b]) HIPCHK(hipEventCreateWithFlags(&ctx->cl_noise[b], hipEventDisableTiming));
+      if (!ctx->cl_roll[b]) HIPCHK(hipEventCreateWithFlags(&ctx->cl_roll[b], hipEventDisableTiming));
+    }
+    // buffer 1 is free once the descriptors are uploaded
+    HIPCHK(hipEventRecord(ctx->cl_roll[1], s));
+  }
+  auto desc_at = [&](uint32_t k) {
+    return reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
+  };
   for (uint32_t k = 0; k < n_up; ++k) {
-    const SolveDesc* dd = reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
-    if ((rc = enqueue_single(ctx, s, dd, p, L, sh))) return rc;   // includes the plant step
+    const SolveDesc* dd = desc_at(k);
+    if (!overlap) {
+      if ((rc = enqueue_single(ctx, s, dd, p, L, sh))) return rc;   // includes the plant step
+    } else {
+      const int b = k & 1, nb = b ^ 1;
+      if (k == 0 && (rc = enqueue_noise(ctx, s, dd, p, L))) return rc;
+      if (k + 1 < n_up) {
+        // buffer nb was last read by the rollout of update k - 1
+        HIPCHK(hipStreamWaitEvent(side, ctx->cl_roll[nb], 0));
+        if ((rc = enqueue_noise(ctx, side, desc_at(k + 1), p, L))) return rc;
+        HIPCHK(hipEventRecord(ctx->cl_noise[nb], side));
+      }
+      if (k > 0) HIPCHK(hipStreamWaitEvent(s, ctx->cl_noise[b], 0));
+      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh, ctx->cl_roll[b]))) return rc;
+    }
     if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
     if (u_applied)
       HIPCHK(hipMemcpyAsync(d_ulog + 3 * k, base + L.off_out + 4 * sizeof(float), sizeof(float) * 3,
@@ -1046,7 +1102,8 @@ int load_tune(brmppi_ctx* ctx) {
       if (comma == std::string::npos) continue;
       const long var = std::strtol(s.c_str() + comma + 1, nullptr, 10);
       const int lanes = variant_lanes((int)var);
-      if (valid_block(blk) && var >= 0 && var <= 3 && (kBuckets[bi] > 0 || var <= 1) && blk % (64 * lanes) == 0)
+      if (valid_block(blk) && var >= 0 && var <= kMaxVariant && (kBuckets[bi] > 0 || var <= 1) &&
+          blk % lanes == 0)
         ctx->shape[bi][sc] = LaunchShape{(uint32_t)blk, (int)var};
     }
     const std::string kb = "\"batch_" + std::to_string(kBuckets[bi]) + "\"";
@@ -1103,8 +1160,8 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
   // launch still covers the device; many samples -> one lane, in-kernel noise
   for (int bi = 0; bi < 5; ++bi) {
     const bool guided = kBuckets[bi] > 0;
-    ctx->shape[bi][0] = LaunchShape{256, guided ? 3 : 1};
-    ctx->shape[bi][1] = LaunchShape{256, guided ? 3 : 1};
+    ctx->shape[bi][0] = LaunchShape{256, guided ? 4 : 1};
+    ctx->shape[bi][1] = LaunchShape{256, guided ? 4 : 1};
     ctx->shape[bi][2] = LaunchShape{256, guided ? 2 : 0};
     ctx->shape[bi][3] = LaunchShape{128, 0};
   }
@@ -1138,6 +1195,10 @@ int brmppi_destroy(brmppi_ctx* ctx) {
   drop_graph(ctx);
   collect_timing(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (int b = 0; b < 2; ++b) {
+    if (ctx->cl_noise[b]) (void)hipEventDestroy(ctx->cl_noise[b]);
+    if (ctx->cl_roll[b]) (void)hipEventDestroy(ctx->cl_roll[b]);
+  }
   ctx->pin.release();
   for (auto& p : ctx->slot_pin) p.release();
   delete ctx;
@@ -1338,7 +1399,7 @@ int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant) {
   }
   if (block < 64 || block > (uint32_t)kMaxBlock || block % 64)
     return fail(BRMPPI_EINVAL, "block must be 64..256, a multiple of 64");
-  if (variant > 3) return fail(BRMPPI_EINVAL, "variant must be 0..3");
+  if (variant > (uint32_t)kMaxVariant) return fail(BRMPPI_EINVAL, "variant must be 0..4");
   ctx->forced = LaunchShape{block, (int)variant};
   drop_graph(ctx);
   return BRMPPI_OK;
@@ -1426,7 +1487,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       float best_ms = 1e30f, best_v0 = 1e30f;
       uint32_t best_v0_block = ctx->batch_block[bi];
       std::string times;             // [block, variant, ms per noise + rollout] of every candidate
-      for (int variant = 0; variant < 4; ++variant) {
+      for (int variant = 0; variant <= kMaxVariant; ++variant) {
         if (bucket == 0 && variant > 1) continue;
         const uint32_t lanes = (uint32_t)variant_lanes(variant);
         for (uint32_t block : {64u, 128u, 256u}) {

@@ -170,7 +170,7 @@ def test_launch_shapes_bitwise_identical(ctx, n_obs, flags):
     ctx.set_path(406, p.path, p.ds)
     B.brmppi_set_launch(ctx.h, 64, 0)
     ref = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=406), want_J=True, want_useq=True)
-    for variant in (0, 1, 2, 3):
+    for variant in (0, 1, 2, 3, 4):
         if flags & W.FLAG_GUIDANCE_OFF and variant > 1:
             continue
         for block in (64, 128, 256):
