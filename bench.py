@@ -156,7 +156,8 @@ def main():
     x_end = B.brmppi_get_state(h, 0)
     value = S * T * args.steps / wall
     roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
-    noise_ms = prof["noise"]["ms"] / prof["noise"]["count"] if prof["noise"]["count"] else 0.0
+    # the closed loop draws the normals of several updates per noise launch
+    noise_ms = prof["noise"]["ms"] / args.steps if prof["noise"]["count"] else 0.0
     # variants 1-3 draw the normals in the separate noise kernel: the rollout
     # kernel's own algorithmic work then excludes the Box-Muller flops
     noise_in_kernel = prof["noise"]["count"] == 0
@@ -185,7 +186,7 @@ def main():
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
             "kernel": "k_rollout (8-obstacle bucket)", "launch_shape": {"block_variant": shape},
-            "noise_kernel_avg_ms": noise_ms, "flops_per_launch": flops, "avg_launch_ms": roll_ms,
+            "noise_kernel_ms_per_update": noise_ms, "noise_launches": prof["noise"]["count"], "flops_per_launch": flops, "avg_launch_ms": roll_ms,
             "launches": prof["rollout"]["count"], "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
             "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
             "flops_per_sample_step": flops_per_sample_step(n_obs),

@@ -60,7 +60,10 @@ int variant_lanes(int variant);
 bool variant_pre(int variant);
 hipError_t launch_rollout(int bucket, int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
                           BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream);
-hipError_t launch_noise(const SolveDesc* desc, uint32_t S, uint32_t T, uint32_t n_normals, hipStream_t stream);
+// normals of `count` instances whose descriptors start at `first`, `stride`
+// bytes apart (all with the same S, T and normals per step)
+hipError_t launch_noise(const SolveDesc* first, size_t stride, uint32_t count, uint32_t S, uint32_t T,
+                        uint32_t n_normals, hipStream_t stream);
 hipError_t launch_reduce(const SolveDesc* descs, const Item* items, uint32_t n_items,
                          BatchCounters* ctr, uint32_t grid, hipStream_t stream);
 hipError_t launch_philox_dump(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t n, uint32_t* out,

@@ -242,7 +242,8 @@ __device__ __forceinline__ float group_bcast(float x) {
     return x;
   } else {
     constexpr int ctrl = (G >= 4) ? (Q * 0x55) : ((Q) | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6));
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), ctrl, 0xF, 0xF, false));
+    // every lane reads an in-range lane of its own quad: no "old" value needed
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, true));
   }
 }
 
@@ -255,8 +256,8 @@ constexpr int kDppHalfMirror = 0x141;
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const int lo = __double2loint(x), hi = __double2hiint(x);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi2, lo2);
 }
 
@@ -463,7 +464,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
     const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
-    const float tn = tg.sd / tg.cd;
+    const float tn = tg.sd * rcp(tg.cd);    // |delta| stays far from pi/2: cos > 0
     const float kd = tn * inv_l1;     // th1_dot = v kd
     const float vkd = v * kd;
     const float Aw2 = sp - ch * cp * tn;
@@ -497,13 +498,31 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
         constexpr int i = decltype(I)::value;
         const int vl = g + G * i;
         Acc5 A = acc_zero();
-        if (hitch && vl < 2) acc_row(A, H[(G == 1) ? vl : 0]);
+        if constexpr (G == 1) {
+          if (hitch && vl < 2) acc_row(A, H[vl]);
+        } else if (i == 0) {
+          // lanes 0 and 1 hold the hitch rows; the others add exact zeros
+          // (an accumulator is never -0, so x + 0 keeps its bits)
+          RowTerms Hz = H[0];
+          if (!(hitch && vl < 2)) Hz.c = Hz.g0 = Hz.g1 = Hz.rr = 0.0f;
+          acc_row(A, Hz);
+        }
 #pragma unroll
         for (int j = i; j < NSL; j += NV) {
           const int o = g + G * j;
-          if (o < n_obs) {
+          if constexpr (G == 1) {
+            if (o < n_obs) {
+              const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+              O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+              acc_row(A, O[j]);
+            }
+          } else if (G * j < n_obs) {
+            // lanes past the last obstacle compute a row from an in-range LDS
+            // slot and contribute zeros, without a divergent branch
             const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
-            O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+            RowTerms Rt = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+            if (!(o < n_obs)) Rt.c = Rt.g0 = Rt.g1 = Rt.rr = Rt.Lf = Rt.ih = 0.0f;
+            O[j] = Rt;
             acc_row(A, O[j]);
           }
         }
@@ -525,7 +544,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 #pragma unroll
       for (int j = 0; j < NSL; ++j) {
         const int o = g + G * j;
-        if (o < n_obs) alpha_o[j] = -(O[j].Lf + O[j].g0 * uj + O[j].g1 * uw) * O[j].ih;
+        if (G == 1 ? (o < n_obs) : (G * j < n_obs)) alpha_o[j] = -(O[j].Lf + O[j].g0 * uj + O[j].g1 * uw) * O[j].ih;
       }
     }
 
@@ -665,10 +684,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
 // ---------------------------------------------------------------------------
 // Noise: every (sample, step, Philox block) in parallel -> [tau][k][S_pad]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_noise(const SolveDesc* __restrict__ dp) {
-  const SolveDesc& d = *dp;
+__global__ __launch_bounds__(256) void k_noise(const char* __restrict__ descs, uint32_t stride, uint32_t nb) {
+  // blockIdx.z = (update u of a run of consecutive descriptors) * nb + Philox block
+  const uint32_t u = blockIdx.z / nb, b = blockIdx.z % nb;
+  const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)u * stride);
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t tau = blockIdx.y, b = blockIdx.z;
+  const uint32_t tau = blockIdx.y;
   if (s >= d.S) return;
   uint32_t r[4];
   float e[4];
@@ -1112,9 +1133,12 @@ int rollout_blocks_per_cu(int bucket, int variant, uint32_t block) {
   }
 }
 
-hipError_t launch_noise(const SolveDesc* desc, uint32_t S, uint32_t T, uint32_t n_normals, hipStream_t stream) {
-  const dim3 grid((S + 255) / 256, T, (n_normals + 3) / 4);
-  hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, stream, desc);
+hipError_t launch_noise(const SolveDesc* first, size_t stride, uint32_t count, uint32_t S, uint32_t T,
+                        uint32_t n_normals, hipStream_t stream) {
+  const uint32_t nb = (n_normals + 3) / 4;
+  if (count == 0 || nb == 0) return hipSuccess;
+  const dim3 grid((S + 255) / 256, T, nb * count);
+  hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, stream, reinterpret_cast<const char*>(first), (uint32_t)stride, nb);
   return hipGetLastError();
 }
 

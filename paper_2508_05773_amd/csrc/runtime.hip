@@ -193,6 +193,8 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0)
 
 // largest precomputed-noise buffer a plain solve may take
 constexpr size_t kMaxNoiseBytes = size_t(512) << 20;
+// closed loop: normals of up to this many bytes are drawn per noise launch
+constexpr size_t kClosedLoopNoiseBytes = size_t(256) << 20;
 
 struct Profile {
   double ms[5] = {0, 0, 0, 0, 0};
@@ -274,10 +276,6 @@ struct brmppi_ctx {
   Profile prof;
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> pending_timing;
-  // closed loop: noise of update k + 1 on a second stream during update k
-  // (events: noise ready / rollout done, per buffer parity)
-  hipEvent_t cl_noise[2] = {nullptr, nullptr};
-  hipEvent_t cl_roll[2] = {nullptr, nullptr};
 
   // served form
   std::mutex mu;                // guards everything below and every device enqueue
@@ -449,13 +447,13 @@ void collect_timing(brmppi_ctx* ctx) {
 int enqueue_noise(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
                   const ScratchLayout& L) {
   if (!L.n_normals) return fail(BRMPPI_EINVAL, "internal: noise buffer missing");
-  return timed(ctx, st, 4, [&] { return launch_noise(d_desc, p.S, p.T, L.n_normals, st); });
+  return timed(ctx, st, 4, [&] { return launch_noise(d_desc, 0, 1, p.S, p.T, L.n_normals, st); });
 }
 
 // rollout + weights + reduce (+ plant) of one instance whose normals, if the
 // shape reads them, are already in its noise buffer (or ordered before on st)
 int enqueue_rollout_reduce(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
-                           const ScratchLayout& L, const LaunchShape& sh, hipEvent_t after_rollout) {
+                           const ScratchLayout& L, const LaunchShape& sh) {
   const int bucket = bucket_for(p.n_obs, p.flags);
   const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
   const uint32_t grid = (p.S + per_tile - 1) / per_tile;
@@ -463,7 +461,6 @@ int enqueue_rollout_reduce(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_d
     return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
   });
   if (rc) return rc;
-  if (after_rollout) HIPCHK(hipEventRecord(after_rollout, st));
   const uint32_t nr = L.n_wchunk * L.n_rgroup;
   return timed(ctx, st, 1, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
 }
@@ -814,12 +811,16 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   const size_t log_off = in_off + round_up(in_bytes, 256);
   const size_t log_end = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
                          round_up(sizeof(float) * 3 * n_up, 256);
-  // the normals of update k + 1 are drawn on a second stream while update k
-  // runs: odd updates read a second noise buffer
-  const bool overlap = variant_pre(sh.variant) && ctx->n_streams >= 2 && n_up > 1;
-  const size_t noise_bytes = (size_t)L.n_normals * p.T * L.S_pad * sizeof(float);
-  const size_t noise2_off = log_end;
-  const size_t need = log_end + (overlap ? round_up(noise_bytes, 256) : 0);
+  // Normals come in chunks of C updates, one noise launch per chunk (slot
+  // k mod C of one chunk-sized region).  Drawing the next chunk on a second
+  // stream while a chunk runs was measured slower: the noise waves delay the
+  // rollout's, each of which is on the critical path of its update.
+  const bool pre = variant_pre(sh.variant);
+  const size_t noise_bytes = round_up((size_t)L.n_normals * p.T * L.S_pad * sizeof(float), 256);
+  uint32_t C = 1;
+  if (pre) C = (uint32_t)std::max<size_t>(1, std::min<size_t>({16, n_up, kClosedLoopNoiseBytes / noise_bytes}));
+  const size_t noise_off = log_end;
+  const size_t need = log_end + (pre ? C * noise_bytes : 0);
   if ((rc = ensure_scratch(ctx, need))) return rc;
   char* base = ctx->scratch.ptr;
   hipStream_t s = ctx->streams[0];
@@ -836,7 +837,7 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
     SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
     // only the first update reads the caller's sequence; later ones the shifted result
     fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out);
-    if (overlap && (k & 1)) hd->noise = reinterpret_cast<float*>(base + noise2_off);
+    if (pre) hd->noise = reinterpret_cast<float*>(base + noise_off + (k % C) * noise_bytes);
   }
   std::memset(pin + ctr_rel, 0, 256);
   if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, sizeof(float) * 3 * p.T);
@@ -848,33 +849,20 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   }
   HIPCHK(hipMemcpyAsync(base + in_off, pin, in_bytes, hipMemcpyHostToDevice, s));
   if (x_out) HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
-  hipStream_t side = ctx->streams[1];
-  if (overlap) {
-    for (int b = 0; b < 2; ++b) {
-      if (!ctx->cl_noise[b]) HIPCHK(hipEventCreateWithFlags(&ctx->cl_noise[b], hipEventDisableTiming));
-      if (!ctx->cl_roll[b]) HIPCHK(hipEventCreateWithFlags(&ctx->cl_roll[b], hipEventDisableTiming));
-    }
-    // buffer 1 is free once the descriptors are uploaded
-    HIPCHK(hipEventRecord(ctx->cl_roll[1], s));
-  }
   auto desc_at = [&](uint32_t k) {
     return reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
   };
   for (uint32_t k = 0; k < n_up; ++k) {
     const SolveDesc* dd = desc_at(k);
-    if (!overlap) {
+    if (!pre) {
       if ((rc = enqueue_single(ctx, s, dd, p, L, sh))) return rc;   // includes the plant step
     } else {
-      const int b = k & 1, nb = b ^ 1;
-      if (k == 0 && (rc = enqueue_noise(ctx, s, dd, p, L))) return rc;
-      if (k + 1 < n_up) {
-        // buffer nb was last read by the rollout of update k - 1
-        HIPCHK(hipStreamWaitEvent(side, ctx->cl_roll[nb], 0));
-        if ((rc = enqueue_noise(ctx, side, desc_at(k + 1), p, L))) return rc;
-        HIPCHK(hipEventRecord(ctx->cl_noise[nb], side));
+      if (k % C == 0) {
+        const uint32_t cnt = std::min(C, n_up - k);
+        rc = timed(ctx, s, 4, [&] { return launch_noise(dd, desc_bytes, cnt, p.S, p.T, L.n_normals, s); });
+        if (rc) return rc;
       }
-      if (k > 0) HIPCHK(hipStreamWaitEvent(s, ctx->cl_noise[b], 0));
-      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh, ctx->cl_roll[b]))) return rc;
+      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh))) return rc;
     }
     if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
     if (u_applied)
@@ -1195,10 +1183,6 @@ int brmppi_destroy(brmppi_ctx* ctx) {
   drop_graph(ctx);
   collect_timing(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  for (int b = 0; b < 2; ++b) {
-    if (ctx->cl_noise[b]) (void)hipEventDestroy(ctx->cl_noise[b]);
-    if (ctx->cl_roll[b]) (void)hipEventDestroy(ctx->cl_roll[b]);
-  }
   ctx->pin.release();
   for (auto& p : ctx->slot_pin) p.release();
   delete ctx;
@@ -1495,7 +1479,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
           const uint32_t grid = (S + per_tile - 1) / per_tile;
           auto run = [&]() -> hipError_t {
             hipError_t e = hipSuccess;
-            if (variant_pre(variant)) e = launch_noise(d_desc, S, T, K, s);
+            if (variant_pre(variant)) e = launch_noise(d_desc, 0, 1, S, T, K, s);
             if (e == hipSuccess) e = launch_rollout(bucket, variant, d_desc, nullptr, grid, nullptr, grid, block, s);
             return e;
           };
