@@ -8,10 +8,16 @@
 
 namespace brm {
 
-constexpr int kWChunk = 1024;     // samples per weight chunk (fixed: results never depend on
-                                  // the launch shape)
+// Canonical reduction structure (fixed: results never depend on the launch
+// shape or on which kernel reduces): units of 32 samples weighted by their own
+// minimum cost, groups of 32 units merged by log-sum-exp, then the groups.
+constexpr int kUnit = 32;                    // samples per unit
+constexpr int kGroupUnits = 32;              // units per group
+constexpr int kWChunk = kUnit * kGroupUnits; // samples per group
 constexpr int kWThreads = 256;    // threads of the reduce kernel
-constexpr int kRowsPerBlock = 4;  // (step, input) rows per reduce work item: one per wave
+constexpr int kRowsPerBlock = 8;  // (step, input) rows per reduce work item: two per wave
+constexpr size_t kFusedLdsMax = 64 * 1024;   // dynamic LDS bound of the fused rollout
+constexpr uint32_t kCtrStride = 32;          // completion counters one 128-B line apart
 constexpr int kPathWin = 1024;    // waypoints staged in LDS per tile
 constexpr int kPathBack = 64;     // of which before the start progress
 constexpr int kMaxBlock = 256;    // rollout block size bound (launch_bounds)
@@ -25,15 +31,20 @@ struct alignas(16) SolveDesc {
   uint32_t S, T, n_obs, flags;
   uint32_t n_path, instance, seed_lo, seed_hi;
   uint32_t S_pad, n_wchunk, n_rgroup, n_ritems;
-  uint32_t x0_resident, n_normals, pad1, pad2;   // n_normals: 5 + n_obs (guided) or 3
+  uint32_t x0_resident, n_normals, fused, ustar_global;   // n_normals: 5 + n_obs (guided) or 3
+  uint32_t n_units, pad1, pad2, pad3;
   const float4* path;           // controller path (absolute coordinates)
   const float* u_nom_in;        // 3T nominal sequence read by the rollout
   float* u_nom_out;             // 3T warm-start slot of the controller (shift target)
   float* u_star;                // [3T][S_pad] applied inputs
   float* J;                     // [S_pad]
-  float4* wpart;                // [n_wchunk] (m_c, Z_c, Z2_c, 0)
-  float* rpart;                 // [n_wchunk][3T] chunk partial sums
-  uint32_t* counter;            // reduce completion counter (self-resetting)
+  float4* wpart;                // [n_wchunk] group partials (m_g, Z_g, Z2_g, 0)
+  float* rpart;                 // [n_wchunk][3T] group row sums
+  float4* upart;                // [n_units] unit partials (m_u, Z_u, Z2_u, 0) (fused rollout)
+  float* urow;                  // [n_units][3T] unit row sums (fused rollout)
+  uint32_t* counter;            // instance completion counter (self-resetting)
+  uint32_t* gctr;               // [n_wchunk * kCtrStride] group completion counters (fused rollout,
+                                // self-resetting)
   float* u_new;                 // [3T] result
   float* stats;                 // [4] J_min, Z, ess, status
   double* plant_x;              // [8] resident plant state
@@ -58,8 +69,21 @@ struct alignas(16) BatchCounters {
 constexpr int kMaxVariant = 4;   // 0: G1 fused noise, 1: G1, 2: G2, 3: G4, 4: G8 (precomputed noise)
 int variant_lanes(int variant);
 bool variant_pre(int variant);
+// lds_bytes > 0: the single instance's tiles reduce themselves (fused epilogue;
+// descs->fused must be set and the tile size a multiple of kUnit)
 hipError_t launch_rollout(int bucket, int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
-                          BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream);
+                          BatchCounters* ctr, uint32_t grid, uint32_t block, size_t lds_bytes, hipStream_t stream);
+// dynamic LDS of the fused epilogue for a tile of `per_tile` samples: the
+// tile's applied inputs [3T][per_tile + 1] (later reused for the n_groups
+// merge scales), costs, weights, unit minima and scales, unit partials
+__host__ __device__ inline size_t fused_lds_region(uint32_t per_tile, uint32_t T, uint32_t n_groups) {
+  const size_t a = (size_t)3 * T * (per_tile + 1);
+  return ((a > n_groups ? a : n_groups) + 3) / 4 * 4;
+}
+__host__ __device__ inline size_t fused_lds_bytes(uint32_t per_tile, uint32_t T, uint32_t n_groups) {
+  return sizeof(float) * (fused_lds_region(per_tile, T, n_groups) + 2 * (size_t)per_tile + 2 * kGroupUnits) +
+         16 * kGroupUnits;
+}
 // normals of `count` instances whose descriptors start at `first`, `stride`
 // bytes apart (all with the same S, T and normals per step)
 hipError_t launch_noise(const SolveDesc* first, size_t stride, uint32_t count, uint32_t S, uint32_t T,

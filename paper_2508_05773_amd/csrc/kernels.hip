@@ -8,12 +8,14 @@
 //               (eqs. (13)-(15)) accumulated; writes the applied inputs
 //               [3T][S] and the cost of every sample.  One or several lanes
 //               per sample; noise drawn in the kernel or read from k_noise.
-//   k_reduce  : per 1024-sample chunk, the min cost and the weights
-//               exp(-(J - m_chunk)/lambda) (Sec. III-B), chunk partials of
-//               sum_s gamma_s u*_s for every (step, input) row; the last block
-//               of the instance merges the chunks (log-sum-exp rescaling),
-//               writes the new nominal sequence (eq. (5)), the receding-horizon
-//               shift and, on request, a closed-loop FP64 plant step (eq. (6)).
+//   k_reduce  : weights exp(-(J - m)/lambda) (Sec. III-B) and the weighted
+//               average of the applied inputs (eq. (5)) from HBM, in units of
+//               32 samples and groups of 32 units merged by log-sum-exp; the
+//               last block writes the new nominal sequence, the receding-
+//               horizon shift and, on request, a closed-loop FP64 plant step
+//               (eq. (6)).  A single-instance rollout whose tiles are whole
+//               units does the same reduction itself from LDS (fused
+//               epilogue): the applied inputs then never reach HBM.
 //
 // A sample's state, barrier rates and row terms stay in registers.  Obstacles
 // (with their shape matrices) and a window of the path are staged in LDS per
@@ -360,9 +362,12 @@ __device__ __forceinline__ float tracking_cost_sc(const brmppi_params& P, const 
 // computed by lane o mod G in its slot o / G.  After the projection every lane
 // holds the same inputs, state and cost.
 template <int NOB, bool GUIDED, int G, bool PRE>
+// s_u / s_J (fused epilogue): the tile's applied inputs [3T][lds_stride] and
+// costs in LDS, at column t_local.
 __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
-                                               int w0, int nw, int k0, float phi0) {
+                                               int w0, int nw, int k0, float phi0, float* s_u, uint32_t lds_stride,
+                                               uint32_t t_local, float* s_J) {
   static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per sample");
   static_assert(PRE || G == 1, "a sample shared by lanes reads precomputed normals");
   constexpr int NSL = GUIDED ? (NOB + G - 1) / G : 1;   // obstacle slots of this lane
@@ -554,11 +559,18 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
                      P.R_w * uw * uw + P.mu * prog * prog;
     J += (double)rc;
 
-    // --- applied inputs [3T][S_pad] ---
+    // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
     if (store) {
-      ustar[(size_t)(3 * tau + 0) * S_pad + s] = uj;
-      ustar[(size_t)(3 * tau + 1) * S_pad + s] = uw;
-      ustar[(size_t)(3 * tau + 2) * S_pad + s] = unu;
+      if (d.ustar_global) {
+        ustar[(size_t)(3 * tau + 0) * S_pad + s] = uj;
+        ustar[(size_t)(3 * tau + 1) * S_pad + s] = uw;
+        ustar[(size_t)(3 * tau + 2) * S_pad + s] = unu;
+      }
+      if (s_u) {
+        s_u[(3 * tau + 0) * lds_stride + t_local] = uj;
+        s_u[(3 * tau + 1) * lds_stride + t_local] = uw;
+        s_u[(3 * tau + 2) * lds_stride + t_local] = unu;
+      }
     }
 
     // --- explicit Euler, eq. (6), plus psi_dot = nu ---
@@ -582,7 +594,394 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   J += (double)tracking_cost(P, rf, px, py, th1, th2);
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
-  if (store) d.J[s] = Jf;
+  if (store) {
+    d.J[s] = Jf;
+    if (s_J) s_J[t_local] = Jf;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Noise: every (sample, step, Philox block) in parallel -> [tau][k][S_pad]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_noise(const char* __restrict__ descs, uint32_t stride, uint32_t nb) {
+  // blockIdx.z = (update u of a run of consecutive descriptors) * nb + Philox block
+  const uint32_t u = blockIdx.z / nb, b = blockIdx.z % nb;
+  const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)u * stride);
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t tau = blockIdx.y;
+  if (s >= d.S) return;
+  uint32_t r[4];
+  float e[4];
+  philox4x32_10(s, tau, b, d.instance, d.seed_lo, d.seed_hi, r);
+  box_muller4(r, e);
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t kk = 4 * b + k;
+    if (kk < d.n_normals) d.noise[((size_t)tau * d.n_normals + kk) * d.S_pad + s] = e[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block reductions (deterministic: fixed butterfly, fixed wave order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Device-scope ordering for the "last block" patterns.  A publisher needs
+// only a release (its stores written back past its XCD's L2 before the
+// counter increment); the block that sees the last increment needs only an
+// acquire (stale lines dropped before it reads).  A full __threadfence() would
+// also invalidate the L2 of every publisher's XCD under blocks still running.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// grab the next work item (persistent) or take blockIdx.x (direct launch)
+__device__ __forceinline__ bool next_item(uint32_t it, uint32_t n_items, uint32_t* ctr_next, uint32_t* s_slot,
+                                          uint32_t& ix) {
+  if (ctr_next) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(ctr_next, 1u);
+    __syncthreads();
+    ix = *s_slot;
+  } else {
+    if (it > 0) return false;
+    ix = blockIdx.x;
+  }
+  ix = __builtin_amdgcn_readfirstlane(ix);
+  return ix < n_items;
+}
+
+__device__ __forceinline__ void finish_persistent(uint32_t* next, uint32_t* done) {
+  if (threadIdx.x == 0) {
+    fence_release();
+    const uint32_t k = atomicAdd(done, 1u);
+    if (k == gridDim.x - 1) {
+      atomicExch(next, 0u);
+      atomicExch(done, 0u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weights, weighted reduction and update (Sec. III-B weights, eq. (5))
+// ---------------------------------------------------------------------------
+// The weights exp(-(J_s - m)/lambda) and the weighted average of the applied
+// inputs are formed in a fixed structure so that the result never depends on
+// the launch shape: a unit of 32 samples takes weights relative to its own
+// minimum, a group of 32 units rescales them to the group minimum, and the
+// last block of the instance rescales the groups to the global minimum
+// (log-sum-exp merges) and writes U_new, the receding-horizon shift and, when
+// asked, the closed-loop plant step.
+
+// FP64 plant step of the closed loop (Sec. II model, inputs clipped to the
+// hard bounds), in two halves so that only the last few operations wait for
+// the merge.  s_plant: [0..5] sin/cos of th1, delta, th1 - th2; [6..13] the
+// state; [14..16] the applied input U_new[0].
+constexpr int kPlantLds = 17;
+// first half (no barrier): lanes 0..7 load the state, lanes 0..2 one sincos each
+__device__ __forceinline__ void plant_prep(const SolveDesc& d, double* s_plant) {
+  const uint32_t t = threadIdx.x;
+  const double* x = d.plant_x;
+  if (t < 8) s_plant[6 + t] = x[t];
+  if (t < 3) {
+    const double ang = t == 0 ? x[4] : (t == 1 ? x[6] : x[4] - x[5]);
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    s_plant[2 * t] = sn;
+    s_plant[2 * t + 1] = cs;
+  }
+}
+// second half, one thread, after a barrier
+__device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s_plant) {
+  const brmppi_params& P = d.prm;
+  double x[8];
+  for (int k = 0; k < 8; ++k) x[k] = s_plant[6 + k];
+  double j = s_plant[14], w = s_plant[15];
+  const double nu = s_plant[16];
+  j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
+  w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
+  const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
+  const double v = x[2], a = x[3];
+  const double s1 = s_plant[0], c1 = s_plant[1];
+  const double tan_dl = s_plant[2] / s_plant[3];
+  const double s12 = s_plant[4], c12 = s_plant[5];
+  double xn[8];
+  xn[0] = x[0] + Ts * v * c1;
+  xn[1] = x[1] + Ts * v * s1;
+  xn[2] = v + Ts * a;
+  xn[3] = a + Ts * j;
+  xn[4] = x[4] + Ts * v / l1 * tan_dl;
+  xn[5] = x[5] + Ts * v / l2 * (s12 - lh / l1 * c12 * tan_dl);
+  xn[6] = x[6] + Ts * w;
+  xn[7] = x[7] + Ts * nu;
+  for (int k = 0; k < 8; ++k) d.plant_x[k] = xn[k];
+}
+
+// block-wide reductions in a fixed order (thread stride, wave butterfly, waves
+// in index order): the same inputs give the same bits on every launch
+__device__ __forceinline__ float block_min(float v, float* s_red) {
+  v = wave_min(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = fminf(r, s_red[w]);
+  return r;
+}
+// two sums with one pair of barriers (s_red: 2 x 4 floats), each in the same
+// order as a single block sum
+__device__ __forceinline__ void block_sum2(float& a, float& b, float* s_red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    s_red[threadIdx.x >> 6] = a;
+    s_red[4 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  float ra = s_red[0], rb = s_red[4];
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) {
+    ra += s_red[w];
+    rb += s_red[4 + w];
+  }
+  a = ra;
+  b = rb;
+}
+
+// Merge of the chunk partials by the last block of an instance: global min
+// m = min_c m_c, chunk scale exp(-(m_c - m)/lambda), Z and sum of squared
+// weights, then U = sum_c scale_c rpart[c] / Z per row (eq. (5)).  Every load
+// is issued by a different thread or unrolled, so the merge costs a few memory
+// latencies, not one per chunk.
+__device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_red, double* s_plant) {
+  const uint32_t nW = d.n_wchunk;
+  const uint32_t R = 3 * d.T;
+  const uint32_t nt = blockDim.x;
+  const bool plant = (d.flags & BRMPPI_ADVANCE_PLANT) != 0;
+  if (plant) plant_prep(d, s_plant);   // overlaps the merge
+  // the first 8 chunk partials of this thread's first row, loaded before the
+  // merge's barriers so that their latency overlaps them
+  constexpr int kPre = 8;
+  const uint32_t r0 = threadIdx.x;
+  float pre[kPre];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? d.rpart[(size_t)k * R + r0] : 0.0f;
+  float mloc = INFINITY;
+  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
+    mloc = fminf(mloc, d.wpart[c].x);
+  }
+  const float m = block_min(mloc, s_red);
+  float zl = 0.0f, z2l = 0.0f;
+  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
+    const float4 w = d.wpart[c];
+    const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
+    s_scale[c] = sc;
+    zl += sc * w.y;
+    z2l += sc * sc * w.z;
+  }
+  block_sum2(zl, z2l, s_red);   // also orders the s_scale stores before the reads below
+  const float Z = zl, Z2 = z2l;
+  const bool ok = (m < INFINITY) && (Z > 0.0f);
+  if (ok) {
+    const float iZ = 1.0f / Z;
+    for (uint32_t r = threadIdx.x; r < R; r += nt) {
+      const float* __restrict__ col = d.rpart + r;
+      float acc = 0.0f;
+      uint32_t c = 0;
+      for (; c + kPre <= nW; c += kPre) {
+        const bool use_pre = (c == 0) && (r == r0);
+        float v[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : col[(size_t)(c + k) * R];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) acc += s_scale[c + k] * v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) {
+        if (c + k < nW) {
+          const float vk = (c == 0 && r == r0) ? pre[k] : col[(size_t)(c + k) * R];
+          acc += s_scale[c + k] * vk;
+        }
+      }
+      const float U = acc * iZ;
+      d.u_new[r] = U;
+      if (plant && r < 3) s_plant[14 + r] = (double)U;
+      // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
+      if (r >= 3) d.u_nom_out[r - 3] = U;
+      if (r + 3 >= R) d.u_nom_out[r] = U;
+    }
+  } else {
+    // every cost non-finite: return the nominal sequence, keep the warm start
+    for (uint32_t r = threadIdx.x; r < R; r += nt) {
+      const float U = d.u_nom_in[r];
+      d.u_new[r] = U;
+      if (plant && r < 3) s_plant[14 + r] = (double)U;
+    }
+  }
+  if (threadIdx.x == 0) {
+    d.stats[0] = m;
+    d.stats[1] = Z;
+    d.stats[2] = ok ? Z * Z / Z2 : 0.0f;
+    d.stats[3] = ok ? (float)BRMPPI_OK : (float)BRMPPI_ENONFINITE;
+  }
+  if (plant) {
+    __syncthreads();                 // U_new[0] from threads 0..2, the state and sines
+    if (threadIdx.x == 0) plant_finish(d, s_plant);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Canonical reduction primitives (Sec. III-B weights and eq. (5)).  The fused
+// rollout epilogue and k_reduce both call exactly these, so a unit's or a
+// group's partial has the same bits whichever kernel computes it.
+// ---------------------------------------------------------------------------
+// weight of a sample relative to its unit's minimum m (0 for non-finite costs
+// and samples past S, which carry J = +inf)
+__device__ __forceinline__ float unit_weight(float j, float m, float inv_lambda) {
+  return (m < INFINITY && j < INFINITY) ? expf(-(j - m) * inv_lambda) : 0.0f;
+}
+// Z_u and the sum of squared weights over the unit's samples, in sample order
+__device__ __forceinline__ void unit_sums(const float* gam, float& z, float& z2) {
+  z = 0.0f;
+  z2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kUnit; ++i) {
+    const float gm = gam[i];
+    z = z + gm;
+    z2 = fmaf(gm, gm, z2);
+  }
+}
+// one term of a unit's row sum: zero weights leave the sum as it is (samples
+// past S hold no data)
+__device__ __forceinline__ float unit_row_term(float acc, float gm, float u) {
+  return gm != 0.0f ? fmaf(gm, u, acc) : acc;
+}
+// scale of a unit (or group) with minimum m inside a merge with minimum mg
+__device__ __forceinline__ float merge_scale(float m, float mg, float inv_lambda) {
+  return (mg < INFINITY && m < INFINITY) ? expf(-(m - mg) * inv_lambda) : 0.0f;
+}
+// group (Z, Z2) from its units' (m_u, Z_u, Z2_u) and scales, in unit order
+__device__ __forceinline__ void group_sums(const float4* up, const float* sig, uint32_t nu, float& z, float& z2) {
+  z = 0.0f;
+  z2 = 0.0f;
+#pragma unroll
+  for (int u = 0; u < kGroupUnits; ++u) {
+    if ((uint32_t)u < nu) {
+      const float sc = sig[u];
+      z = fmaf(sc, up[u].y, z);
+      z2 = fmaf(sc * sc, up[u].z, z2);
+    }
+  }
+}
+
+// Group merge by the last tile of the group: m_g, unit scales, (Z_g, Z2_g)
+// and the group row sums from the units' partials.
+__device__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint32_t nu_g, float* s_sig,
+                            float4* s_up, float* s_red) {
+  const uint32_t t = threadIdx.x, nt = blockDim.x, R = 3 * d.T;
+  // this thread's first row: all the group's unit sums, loaded before the
+  // minimum (they do not depend on it)
+  float v0[kGroupUnits];
+  {
+    const float* __restrict__ col = d.urow + (size_t)gu0 * R + (t < R ? t : 0);
+#pragma unroll
+    for (int u = 0; u < kGroupUnits; ++u) v0[u] = (t < R && (uint32_t)u < nu_g) ? col[(size_t)u * R] : 0.0f;
+  }
+  float4 up = make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
+  if (t < nu_g) up = d.upart[gu0 + t];
+  const float mg = block_min(up.x, s_red);
+  if (t < nu_g) {
+    s_up[t] = up;
+    s_sig[t] = merge_scale(up.x, mg, d.inv_lambda);
+  }
+  __syncthreads();
+  if (t == 0) {
+    float z, z2;
+    group_sums(s_up, s_sig, nu_g, z, z2);
+    d.wpart[grp] = make_float4(mg, z, z2, 0.0f);
+  }
+  for (uint32_t r = t; r < R; r += nt) {
+    // all the group's unit sums of this row are loaded at once: one latency
+    const float* __restrict__ col = d.urow + (size_t)gu0 * R + r;
+    float v[kGroupUnits];
+#pragma unroll
+    for (int u = 0; u < kGroupUnits; ++u)
+      v[u] = (r == t) ? v0[u] : (((uint32_t)u < nu_g) ? col[(size_t)u * R] : 0.0f);
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kGroupUnits; ++u)
+      if ((uint32_t)u < nu_g) acc = unit_row_term(acc, s_sig[u], v[u]);
+    d.rpart[(size_t)grp * R + r] = acc;
+  }
+}
+
+// Fused reduction of one tile (its samples' costs and applied inputs are in
+// LDS): unit weights, unit partials to HBM; the last tile of each group merges
+// the group, the last group the instance (U_new, shift, plant step).
+__device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile, float* s_u, uint32_t lds_stride,
+                              const float* s_J, float* s_gam, float* s_mu, float* s_sig, float4* s_up,
+                              float* s_red, double* s_trig, uint32_t* s_flag) {
+  const uint32_t t = threadIdx.x, nt = blockDim.x, R = 3 * d.T;
+  const uint32_t k_units = per_tile / kUnit;
+  const uint32_t u0 = s0 / kUnit;
+  const uint32_t nu_tile = min(k_units, d.n_units - u0);
+  // unit minimum (exact in any order) and weights; a unit is half a wave
+  if (t < per_tile) {
+    const float j = s_J[t];
+    float m = j;
+#pragma unroll
+    for (int o = kUnit / 2; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    s_gam[t] = unit_weight(j, m, d.inv_lambda);
+    if ((t & (kUnit - 1)) == 0) s_mu[t / kUnit] = m;
+  }
+  __syncthreads();
+  if (t < nu_tile) {
+    float z, z2;
+    unit_sums(s_gam + kUnit * t, z, z2);
+    d.upart[u0 + t] = make_float4(s_mu[t], z, z2, 0.0f);
+  }
+  for (uint32_t it = t; it < nu_tile * R; it += nt) {
+    const uint32_t j = it / R, r = it - j * R;
+    const float* gam = s_gam + kUnit * j;
+    const float* u = s_u + r * lds_stride + kUnit * j;
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kUnit; ++i) acc = unit_row_term(acc, gam[i], u[i]);
+    d.urow[(size_t)(u0 + j) * R + r] = acc;
+  }
+  // publish the tile's units; the last tile of the group merges it
+  const uint32_t grp = u0 / kGroupUnits, gu0 = grp * kGroupUnits;
+  const uint32_t nu_g = min((uint32_t)kGroupUnits, d.n_units - gu0);
+  const uint32_t tiles_g = (nu_g + k_units - 1) / k_units;
+  __syncthreads();
+  if (t == 0) {
+    fence_release();
+    *s_flag = (atomicAdd(&d.gctr[grp * kCtrStride], 1u) == tiles_g - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (*s_flag == 0u) return;
+  fence_acquire();
+  group_merge(d, grp, gu0, nu_g, s_sig, s_up, s_red);
+  if (t == 0) atomicExch(&d.gctr[grp * kCtrStride], 0u);
+  // publish the group; the last group merges the instance
+  __syncthreads();
+  if (t == 0) {
+    fence_release();
+    *s_flag = (atomicAdd(d.counter, 1u) == d.n_wchunk - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (*s_flag == 0u) return;
+  fence_acquire();
+  finalize_instance(d, s_u, s_red, s_trig);   // the inputs' LDS is free: merge scales
+  if (t == 0) atomicExch(d.counter, 0u);
 }
 
 template <int NOB, bool GUIDED, int G, bool PRE>
@@ -591,8 +990,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
                                                        BatchCounters* __restrict__ ctr) {
   __shared__ float4 s_path[kPathWin];
   __shared__ ObsL s_obs[BRMPPI_MAX_OBS];
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_tile, s_flag;
+  __shared__ float s_red[2 * (kMaxBlock / 64)];
+  __shared__ double s_trig[kPlantLds];
+  extern __shared__ float s_dyn[];            // fused epilogue only
   const uint32_t per_tile = blockDim.x / G;   // samples per tile
+  const uint32_t lds_stride = per_tile + 1;
   for (uint32_t it = 0;; ++it) {
     uint32_t tix;
     if (ctr) {
@@ -660,19 +1063,36 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
       w.y -= oy;
       s_path[j] = w;
     }
+    // fused epilogue (direct launch of one instance): LDS for the tile's
+    // applied inputs, costs (+inf where no sample stores), weights, units
+    const bool fused = (ctr == nullptr) && d.fused;
+    float *s_u = nullptr, *s_J = nullptr, *s_gam = nullptr, *s_mu = nullptr, *s_sig = nullptr;
+    float4* s_up = nullptr;
+    if (fused) {
+      s_u = s_dyn;
+      s_J = s_dyn + fused_lds_region(per_tile, d.T, d.n_wchunk);
+      s_gam = s_J + per_tile;
+      s_mu = s_gam + per_tile;
+      s_sig = s_mu + kGroupUnits;
+      s_up = reinterpret_cast<float4*>(s_sig + kGroupUnits);
+      for (uint32_t i = threadIdx.x; i < per_tile; i += blockDim.x) s_J[i] = INFINITY;
+    }
     __syncthreads();
 
     // every lane runs (lanes past S repeat the last sample and do not store),
     // so the group-wide DPP broadcasts always read active lanes
-    const uint32_t s_raw = tl.s0 + threadIdx.x / G;
+    const uint32_t t_local = threadIdx.x / G;
+    const uint32_t s_raw = tl.s0 + t_local;
     const int g = (int)(threadIdx.x % G);
     const bool valid = s_raw < d.S;
     const uint32_t s = valid ? s_raw : d.S - 1;
-    rollout_sample<NOB, GUIDED, G, PRE>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0);
+    rollout_sample<NOB, GUIDED, G, PRE>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
+                                        lds_stride, t_local, s_J);
     __syncthreads();
+    if (fused) tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);
   }
   if (ctr && threadIdx.x == 0) {
-    __threadfence();
+    fence_release();
     const uint32_t done = atomicAdd(&ctr->tile_done, 1u);
     if (done == gridDim.x - 1) {
       atomicExch(&ctr->tile_next, 0u);
@@ -681,228 +1101,33 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
   }
 }
 
-// ---------------------------------------------------------------------------
-// Noise: every (sample, step, Philox block) in parallel -> [tau][k][S_pad]
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_noise(const char* __restrict__ descs, uint32_t stride, uint32_t nb) {
-  // blockIdx.z = (update u of a run of consecutive descriptors) * nb + Philox block
-  const uint32_t u = blockIdx.z / nb, b = blockIdx.z % nb;
-  const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)u * stride);
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t tau = blockIdx.y;
-  if (s >= d.S) return;
-  uint32_t r[4];
-  float e[4];
-  philox4x32_10(s, tau, b, d.instance, d.seed_lo, d.seed_hi, r);
-  box_muller4(r, e);
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t kk = 4 * b + k;
-    if (kk < d.n_normals) d.noise[((size_t)tau * d.n_normals + kk) * d.S_pad + s] = e[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Block reductions (deterministic: fixed butterfly, fixed wave order)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, 64));
-  return v;
-}
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-// grab the next work item (persistent) or take blockIdx.x (direct launch)
-__device__ __forceinline__ bool next_item(uint32_t it, uint32_t n_items, uint32_t* ctr_next, uint32_t* s_slot,
-                                          uint32_t& ix) {
-  if (ctr_next) {
-    if (threadIdx.x == 0) *s_slot = atomicAdd(ctr_next, 1u);
-    __syncthreads();
-    ix = *s_slot;
-  } else {
-    if (it > 0) return false;
-    ix = blockIdx.x;
-  }
-  ix = __builtin_amdgcn_readfirstlane(ix);
-  return ix < n_items;
-}
-
-__device__ __forceinline__ void finish_persistent(uint32_t* next, uint32_t* done) {
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t k = atomicAdd(done, 1u);
-    if (k == gridDim.x - 1) {
-      atomicExch(next, 0u);
-      atomicExch(done, 0u);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Weights, weighted reduction and update (Sec. III-B weights, eq. (5))
-// ---------------------------------------------------------------------------
-// Work item = (chunk of 1024 samples, group of 4 rows of the [3T][S] applied
-// inputs).  Every block of a chunk recomputes the chunk's weights
-// gamma_s = exp(-(J_s - m_c)/lambda) from the chunk's 4 KB of costs (same code,
-// same order: same values) and stages them in LDS; the first row group also
-// stores (m_c, Z_c, Z2_c).  Wave w sums gamma_s u*[r][s] over the chunk for
-// row r = 4 rg + w with coalesced float4 loads.  The last block of the
-// instance rescales every chunk by exp(-(m_c - m)/lambda) (log-sum-exp merge),
-// writes U_new, the receding-horizon shift and, when asked, the closed-loop
-// plant step.
-
-// FP64 plant step of the closed loop (Sec. II model, inputs clipped to the
-// hard bounds).  The three angles whose sine and cosine it needs go to three
-// lanes of wave 0, one sincos each, so that their latencies overlap.
-__device__ void plant_step(const SolveDesc& d, double* s_trig) {
-  const brmppi_params& P = d.prm;
-  const uint32_t t = threadIdx.x;
-  if (t < 3) {
-    const double* x = d.plant_x;
-    const double ang = t == 0 ? x[4] : (t == 1 ? x[6] : x[4] - x[5]);
-    double sn, cs;
-    sincos(ang, &sn, &cs);
-    s_trig[2 * t] = sn;
-    s_trig[2 * t + 1] = cs;
-  }
-  __syncthreads();
-  if (t == 0) {
-    double x[8];
-    for (int k = 0; k < 8; ++k) x[k] = d.plant_x[k];
-    double j = d.u_new[0], w = d.u_new[1], nu = d.u_new[2];
-    j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
-    w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
-    const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
-    const double v = x[2], a = x[3];
-    const double s1 = s_trig[0], c1 = s_trig[1];
-    const double tan_dl = s_trig[2] / s_trig[3];
-    const double s12 = s_trig[4], c12 = s_trig[5];
-    double xn[8];
-    xn[0] = x[0] + Ts * v * c1;
-    xn[1] = x[1] + Ts * v * s1;
-    xn[2] = v + Ts * a;
-    xn[3] = a + Ts * j;
-    xn[4] = x[4] + Ts * v / l1 * tan_dl;
-    xn[5] = x[5] + Ts * v / l2 * (s12 - lh / l1 * c12 * tan_dl);
-    xn[6] = x[6] + Ts * w;
-    xn[7] = x[7] + Ts * nu;
-    for (int k = 0; k < 8; ++k) d.plant_x[k] = xn[k];
-  }
-}
-
-// block-wide reductions in a fixed order (thread stride, wave butterfly, waves
-// in index order): the same inputs give the same bits on every launch
-__device__ __forceinline__ float block_min(float v, float* s_red) {
-  v = wave_min(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  float r = s_red[0];
-  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = fminf(r, s_red[w]);
-  return r;
-}
-__device__ __forceinline__ float block_sum(float v, float* s_red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  float r = s_red[0];
-  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r += s_red[w];
-  return r;
-}
-
-// Merge of the chunk partials by the last block of an instance: global min
-// m = min_c m_c, chunk scale exp(-(m_c - m)/lambda), Z and sum of squared
-// weights, then U = sum_c scale_c rpart[c] / Z per row (eq. (5)).  Every load
-// is issued by a different thread or unrolled, so the merge costs a few memory
-// latencies, not one per chunk.
-__device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_red, double* s_trig) {
-  const uint32_t nW = d.n_wchunk;
-  const uint32_t R = 3 * d.T;
-  const uint32_t nt = blockDim.x;
-  // the first 8 chunk partials of this thread's first row, loaded before the
-  // merge's barriers so that their latency overlaps them
-  constexpr int kPre = 8;
-  const uint32_t r0 = threadIdx.x;
-  float pre[kPre];
-#pragma unroll
-  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? d.rpart[(size_t)k * R + r0] : 0.0f;
-  float mloc = INFINITY;
-  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
-    mloc = fminf(mloc, d.wpart[c].x);
-  }
-  const float m = block_min(mloc, s_red);
-  float zl = 0.0f, z2l = 0.0f;
-  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
-    const float4 w = d.wpart[c];
-    const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
-    s_scale[c] = sc;
-    zl += sc * w.y;
-    z2l += sc * sc * w.z;
-  }
-  const float Z = block_sum(zl, s_red);
-  const float Z2 = block_sum(z2l, s_red);   // also orders the s_scale stores before the reads below
-  const bool ok = (m < INFINITY) && (Z > 0.0f);
-  if (ok) {
-    const float iZ = 1.0f / Z;
-    for (uint32_t r = threadIdx.x; r < R; r += nt) {
-      const float* __restrict__ col = d.rpart + r;
-      float acc = 0.0f;
-      uint32_t c = 0;
-      for (; c + kPre <= nW; c += kPre) {
-        const bool use_pre = (c == 0) && (r == r0);
-        float v[kPre];
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : col[(size_t)(c + k) * R];
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) acc += s_scale[c + k] * v[k];
-      }
-#pragma unroll
-      for (int k = 0; k < kPre; ++k) {
-        if (c + k < nW) {
-          const float vk = (c == 0 && r == r0) ? pre[k] : col[(size_t)(c + k) * R];
-          acc += s_scale[c + k] * vk;
-        }
-      }
-      const float U = acc * iZ;
-      d.u_new[r] = U;
-      // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
-      if (r >= 3) d.u_nom_out[r - 3] = U;
-      if (r + 3 >= R) d.u_nom_out[r] = U;
-    }
-  } else {
-    // every cost non-finite: return the nominal sequence, keep the warm start
-    for (uint32_t r = threadIdx.x; r < R; r += nt) d.u_new[r] = d.u_nom_in[r];
-  }
-  if (threadIdx.x == 0) {
-    d.stats[0] = m;
-    d.stats[1] = Z;
-    d.stats[2] = ok ? Z * Z / Z2 : 0.0f;
-    d.stats[3] = ok ? (float)BRMPPI_OK : (float)BRMPPI_ENONFINITE;
-  }
-  if (d.flags & BRMPPI_ADVANCE_PLANT) {
-    __syncthreads();                 // u_new[0..2] written by threads 0..2
-    plant_step(d, s_trig);
-  }
-}
-
 constexpr uint32_t kMaxWChunks = BRMPPI_MAX_S / kWChunk;
-static_assert(kRowsPerBlock == kWThreads / 64, "one wave per row");
-static_assert(kWChunk == 4 * kWThreads, "one float4 of samples per thread");
+static_assert(kRowsPerBlock == 2 * (kWThreads / 64), "two rows per wave");
+static_assert(kWChunk == 4 * kWThreads, "four samples per thread");
+static_assert(kUnit == 32 && kGroupUnits == 32, "a unit is half a wave; a group's units fit one wave");
 
+// Reduction from the applied inputs in HBM (batched launches and tiles that
+// are not whole units), with the same canonical structure as the fused
+// epilogue.  Work item = (group of 1024 samples, 8 rows): the group's unit
+// weights are recomputed from its 4 KB of costs (same code: same values), the
+// first row block also stores the group's (m_g, Z_g, Z2_g).  Half-wave h of
+// wave w takes row 8 rg + 2 w + h, lane u of it unit u's 32 samples; the unit
+// sums are merged in unit order by one thread per row.  The last block of the
+// instance merges the groups.
 __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restrict__ descs,
                                                      const Item* __restrict__ items, uint32_t n_items,
                                                      BatchCounters* __restrict__ ctr) {
-  __shared__ float4 s_gam[kWChunk / 4];
-  __shared__ float s_red[3][kWThreads / 64];
+  __shared__ float4 s_gam4[kWChunk / 4];
+  __shared__ float s_mu[kGroupUnits], s_sig[kGroupUnits];
+  __shared__ float4 s_up[kGroupUnits];
+  __shared__ float s_R[kRowsPerBlock][kGroupUnits];
+  __shared__ float s_red[2 * (kWThreads / 64)];
   __shared__ float s_scale[kMaxWChunks];
-  __shared__ double s_trig[6];
+  __shared__ double s_trig[kPlantLds];
   __shared__ uint32_t s_slot, s_last;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t t = threadIdx.x;
+  const int lane = t & 63, wid = t >> 6;
+  const float* s_gam = reinterpret_cast<const float*>(s_gam4);
   for (uint32_t it = 0;; ++it) {
     uint32_t ix;
     if (!next_item(it, n_items, ctr ? &ctr->r_next : nullptr, &s_slot, ix)) break;
@@ -914,25 +1139,27 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       item.idx = ix;
     }
     const SolveDesc& d = descs[__builtin_amdgcn_readfirstlane(item.inst)];
-    const uint32_t chunk = item.idx / d.n_rgroup, rg = item.idx % d.n_rgroup;
-    const uint32_t base = chunk * kWChunk;
+    const uint32_t grp = item.idx / d.n_rgroup, rg = item.idx % d.n_rgroup;
+    const uint32_t base = grp * kWChunk;
     const uint32_t R = 3 * d.T;
     const uint32_t S = d.S;
+    const uint32_t gu0 = grp * kGroupUnits;
+    const uint32_t nu_g = min((uint32_t)kGroupUnits, d.n_units - gu0);
 
-    // this wave's row of the chunk is loaded first so that its latency
-    // overlaps the costs' load and the weights
-    const uint32_t r = rg * kRowsPerBlock + wid;
-    constexpr int kRowLoads = kWChunk / 4 / 64;
-    float4 urow[kRowLoads];
+    // this lane's row and unit; its 32 applied inputs are loaded first so that
+    // their latency overlaps the weights
+    const uint32_t h = (uint32_t)lane >> 5, u = (uint32_t)lane & 31u;
+    const uint32_t rl = 2 * wid + h;
+    const uint32_t r = rg * kRowsPerBlock + rl;
+    const bool rv = (r < R) && (u < nu_g);
+    float4 uv[kUnit / 4];
+    const float* __restrict__ rowp = d.u_star + (size_t)(rv ? r : 0) * d.S_pad + base + kUnit * u;
 #pragma unroll
-    for (int k = 0; k < kRowLoads; ++k) {
-      const uint32_t s = base + 4 * (lane + 64 * k);
-      urow[k] = (r < R && s < d.S_pad) ? *reinterpret_cast<const float4*>(d.u_star + (size_t)r * d.S_pad + s)
-                                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
+    for (int k = 0; k < kUnit / 4; ++k)
+      uv[k] = rv ? *reinterpret_cast<const float4*>(rowp + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
-    // --- the chunk's weights (thread t: samples base + 4t .. base + 4t + 3) ---
-    const uint32_t s4 = base + 4 * threadIdx.x;
+    // costs (thread t: samples 4t .. 4t + 3 of the group; unit t / 8)
+    const uint32_t s4 = base + 4 * t;
     float jv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     if (s4 < d.S_pad) {
       const float4 q = *reinterpret_cast<const float4*>(d.J + s4);
@@ -947,71 +1174,69 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       if (!(s4 + k < S) || !(jv[k] < INFINITY)) jv[k] = INFINITY;  // past S or NaN -> weight 0
       m = fminf(m, jv[k]);
     }
-    m = wave_min(m);
-    if (lane == 0) s_red[0][wid] = m;
+    m = fminf(m, __shfl_xor(m, 1, 64));
+    m = fminf(m, __shfl_xor(m, 2, 64));
+    m = fminf(m, __shfl_xor(m, 4, 64));
+    s_gam4[t] = make_float4(unit_weight(jv[0], m, d.inv_lambda), unit_weight(jv[1], m, d.inv_lambda),
+                            unit_weight(jv[2], m, d.inv_lambda), unit_weight(jv[3], m, d.inv_lambda));
+    if ((t & 7) == 0) s_mu[t >> 3] = m;
     __syncthreads();
-    m = s_red[0][0];
+    // group minimum and unit scales
+    if (wid == 0) {
+      float mg = (lane < (int)nu_g) ? s_mu[lane] : INFINITY;
 #pragma unroll
-    for (int w = 1; w < kWThreads / 64; ++w) m = fminf(m, s_red[0][w]);
-    const bool any = m < INFINITY;
-    float g[4], z = 0.0f, z2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      g[k] = (any && jv[k] < INFINITY) ? expf(-(jv[k] - m) * d.inv_lambda) : 0.0f;
-      z += g[k];
-      z2 += g[k] * g[k];
-    }
-    s_gam[threadIdx.x] = make_float4(g[0], g[1], g[2], g[3]);
-    if (rg == 0) {
-      z = wave_sum(z);
-      z2 = wave_sum(z2);
-      if (lane == 0) {
-        s_red[1][wid] = z;
-        s_red[2][wid] = z2;
+      for (int o = 32; o >= 1; o >>= 1) mg = fminf(mg, __shfl_xor(mg, o, 64));
+      if (lane < (int)nu_g) {
+        s_sig[lane] = merge_scale(s_mu[lane], mg, d.inv_lambda);
+        if (rg == 0) {
+          float z, z2;
+          unit_sums(s_gam + kUnit * lane, z, z2);
+          s_up[lane] = make_float4(s_mu[lane], z, z2, 0.0f);
+        }
       }
+      if (lane == 0) s_red[0] = mg;
     }
-    __syncthreads();
-    if (rg == 0 && threadIdx.x == 0) {
-      float Z = 0.0f, Z2 = 0.0f;
-#pragma unroll
-      for (int w = 0; w < kWThreads / 64; ++w) {
-        Z += s_red[1][w];
-        Z2 += s_red[2][w];
-      }
-      d.wpart[chunk] = make_float4(m, Z, Z2, 0.0f);
-    }
-
-    // --- one wave per row: sum_s gamma_s u*[r][s] over the chunk ---
-    if (r < R) {
+    // unit row sums, in sample order
+    if (rv) {
+      const float* gam = s_gam + kUnit * u;
       float acc = 0.0f;
 #pragma unroll
-      for (int k = 0; k < kRowLoads; ++k) {
-        const uint32_t i4 = lane + 64 * k;
-        const uint32_t s = base + 4 * i4;
-        const float4 u = urow[k];
-        const float4 w = s_gam[i4];
-        // samples past S hold no data: select, never multiply
-        acc += (s + 0 < S) ? w.x * u.x : 0.0f;
-        acc += (s + 1 < S) ? w.y * u.y : 0.0f;
-        acc += (s + 2 < S) ? w.z * u.z : 0.0f;
-        acc += (s + 3 < S) ? w.w * u.w : 0.0f;
+      for (int k = 0; k < kUnit / 4; ++k) {
+        acc = unit_row_term(acc, gam[4 * k + 0], uv[k].x);
+        acc = unit_row_term(acc, gam[4 * k + 1], uv[k].y);
+        acc = unit_row_term(acc, gam[4 * k + 2], uv[k].z);
+        acc = unit_row_term(acc, gam[4 * k + 3], uv[k].w);
       }
-      acc = wave_sum(acc);
-      if (lane == 0) d.rpart[(size_t)chunk * R + r] = acc;
+      s_R[rl][u] = acc;
     }
-    // publish: the barrier completes every wave's stores to this CU's L2
-    // slice, one device-scope fence then makes them visible to the last block
     __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
+    if (rg == 0 && t == 0) {
+      float z, z2;
+      group_sums(s_up, s_sig, nu_g, z, z2);
+      d.wpart[grp] = make_float4(s_red[0], z, z2, 0.0f);
+    }
+    // group row sums, in unit order
+    if (t < kRowsPerBlock) {
+      const uint32_t rr = rg * kRowsPerBlock + t;
+      if (rr < R) {
+        float acc = 0.0f;
+        for (uint32_t v = 0; v < nu_g; ++v) acc = unit_row_term(acc, s_sig[v], s_R[t][v]);
+        d.rpart[(size_t)grp * R + rr] = acc;
+      }
+    }
+    // publish: the barrier completes every wave's stores, one release by
+    // thread 0 then makes them visible to the block that finishes the instance
+    __syncthreads();
+    if (t == 0) {
+      fence_release();
       const uint32_t k = atomicAdd(d.counter, 1u);
       s_last = (k == d.n_ritems - 1) ? 1u : 0u;
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();
-      finalize_instance(d, s_scale, s_red[0], s_trig);
-      if (threadIdx.x == 0) atomicExch(d.counter, 0u);
+      fence_acquire();
+      finalize_instance(d, s_scale, s_red, s_trig);
+      if (t == 0) atomicExch(d.counter, 0u);
     }
     __syncthreads();
   }
@@ -1061,39 +1286,40 @@ bool variant_pre(int variant) { return variant != 0; }
 
 template <int NOB, bool GD, int G, bool PRE>
 static hipError_t launch_rollout_t(const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
-                                   BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
-  hipLaunchKernelGGL((k_rollout<NOB, GD, G, PRE>), dim3(grid), dim3(block), 0, stream, descs, tiles, n_tiles, ctr);
+                                   BatchCounters* ctr, uint32_t grid, uint32_t block, size_t lds,
+                                   hipStream_t stream) {
+  hipLaunchKernelGGL((k_rollout<NOB, GD, G, PRE>), dim3(grid), dim3(block), lds, stream, descs, tiles, n_tiles, ctr);
   return hipGetLastError();
 }
 
 template <int NOB, bool GD>
 static hipError_t launch_variant(int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
-                                 BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
+                                 BatchCounters* ctr, uint32_t grid, uint32_t block, size_t lds, hipStream_t stream) {
   switch (variant) {
-    case 0: return launch_rollout_t<NOB, GD, 1, false>(descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 1: return launch_rollout_t<NOB, GD, 1, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 0: return launch_rollout_t<NOB, GD, 1, false>(descs, tiles, n_tiles, ctr, grid, block, lds, stream);
+    case 1: return launch_rollout_t<NOB, GD, 1, true>(descs, tiles, n_tiles, ctr, grid, block, lds, stream);
     case 2:
-      if constexpr (GD) return launch_rollout_t<NOB, GD, 2, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 2, true>(descs, tiles, n_tiles, ctr, grid, block, lds, stream);
       return hipErrorInvalidValue;
     case 3:
-      if constexpr (GD) return launch_rollout_t<NOB, GD, 4, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 4, true>(descs, tiles, n_tiles, ctr, grid, block, lds, stream);
       return hipErrorInvalidValue;
     case 4:
-      if constexpr (GD) return launch_rollout_t<NOB, GD, 8, true>(descs, tiles, n_tiles, ctr, grid, block, stream);
+      if constexpr (GD) return launch_rollout_t<NOB, GD, 8, true>(descs, tiles, n_tiles, ctr, grid, block, lds, stream);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_rollout(int bucket, int variant, const SolveDesc* descs, const Tile* tiles, uint32_t n_tiles,
-                          BatchCounters* ctr, uint32_t grid, uint32_t block, hipStream_t stream) {
+                          BatchCounters* ctr, uint32_t grid, uint32_t block, size_t lds, hipStream_t stream) {
   if (block == 0 || block > (uint32_t)kMaxBlock || (block % 64) != 0) return hipErrorInvalidValue;
   switch (bucket) {
-    case 0: return launch_variant<0, false>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 2: return launch_variant<2, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 8: return launch_variant<8, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 16: return launch_variant<16, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
-    case 32: return launch_variant<32, true>(variant, descs, tiles, n_tiles, ctr, grid, block, stream);
+    case 0: return launch_variant<0, false>(variant, descs, tiles, n_tiles, ctr, grid, block, lds, stream);
+    case 2: return launch_variant<2, true>(variant, descs, tiles, n_tiles, ctr, grid, block, lds, stream);
+    case 8: return launch_variant<8, true>(variant, descs, tiles, n_tiles, ctr, grid, block, lds, stream);
+    case 16: return launch_variant<16, true>(variant, descs, tiles, n_tiles, ctr, grid, block, lds, stream);
+    case 32: return launch_variant<32, true>(variant, descs, tiles, n_tiles, ctr, grid, block, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -145,8 +145,9 @@ struct Controller {
 // layout of one instance's scratch inside a block (off_out: [stats(4) | u_new(3T)]
 // for the plain and closed-loop paths; batches pack their outputs elsewhere)
 struct ScratchLayout {
-  size_t off_ustar, off_J, off_wpart, off_rpart, off_out, off_noise, bytes;
+  size_t off_ustar, off_J, off_wpart, off_rpart, off_upart, off_urow, off_out, off_noise, bytes;
   uint32_t S_pad, n_wchunk, n_rgroup, n_normals;  // n_normals > 0: a noise buffer is included
+  uint32_t n_units;
 };
 
 // one instance's uploaded inputs: [descriptor | reduce counter (zero) | nominal
@@ -155,10 +156,16 @@ struct InputBlock {
   size_t counter, unom, bytes;
 };
 
-InputBlock input_block(uint32_t T, bool with_unom) {
+// counters: the instance's, then one per group (fused epilogue), each on its
+// own 128-B line so that the groups' atomics do not contend
+size_t counter_bytes(uint32_t n_groups) {
+  return round_up(sizeof(uint32_t) * kCtrStride * (1 + (size_t)n_groups), 256);
+}
+
+InputBlock input_block(uint32_t T, bool with_unom, uint32_t n_groups) {
   InputBlock b;
   b.counter = (sizeof(SolveDesc) + 255) / 256 * 256;
-  b.unom = b.counter + 256;
+  b.unom = b.counter + counter_bytes(n_groups);
   b.bytes = b.unom + (with_unom ? sizeof(float) * 3 * T : 0);
   return b;
 }
@@ -173,6 +180,7 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0)
   L.n_normals = noise_normals;
   L.S_pad = (uint32_t)round_up(S, 256);
   L.n_wchunk = (S + kWChunk - 1) / kWChunk;
+  L.n_units = (S + kUnit - 1) / kUnit;
   L.n_rgroup = (3 * T + kRowsPerBlock - 1) / kRowsPerBlock;
   size_t o = 0;
   L.off_ustar = o;
@@ -183,6 +191,10 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0)
   o = round_up(o + (size_t)L.n_wchunk * sizeof(float4), 256);
   L.off_rpart = o;
   o = round_up(o + (size_t)L.n_wchunk * 3 * T * sizeof(float), 256);
+  L.off_upart = o;
+  o = round_up(o + (size_t)L.n_units * sizeof(float4), 256);
+  L.off_urow = o;
+  o = round_up(o + (size_t)L.n_units * 3 * T * sizeof(float), 256);
   L.off_out = o;
   o = round_up(o + (size_t)(4 + 3 * T) * sizeof(float), 256);
   L.off_noise = o;
@@ -344,8 +356,12 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
 
 // base: the instance's scratch; unom_dev: device copy of p.u_nom when the
 // caller supplied one; counter: a zeroed u32; out: [stats(4) | u_new(3T)]
+// fused: the rollout reduces its own tiles (counter must be followed by
+// n_wchunk zeroed group counters); ustar_global: the applied inputs are also
+// written to HBM (always when k_reduce reduces)
 void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const ScratchLayout& L, char* base,
-               uint32_t seed_offset, const float* unom_dev, uint32_t* counter, float* out) {
+               uint32_t seed_offset, const float* unom_dev, uint32_t* counter, float* out, bool fused = false,
+               bool ustar_global = true) {
   std::memset(&d, 0, sizeof(d));
   d.prm = *p.params;
   d.lambda = p.lambda;
@@ -376,6 +392,12 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.wpart = reinterpret_cast<float4*>(base + L.off_wpart);
   d.rpart = reinterpret_cast<float*>(base + L.off_rpart);
   d.counter = counter;
+  d.n_units = L.n_units;
+  d.upart = reinterpret_cast<float4*>(base + L.off_upart);
+  d.urow = reinterpret_cast<float*>(base + L.off_urow);
+  d.fused = fused ? 1u : 0u;
+  d.ustar_global = (!fused || ustar_global) ? 1u : 0u;
+  d.gctr = fused ? counter + kCtrStride : nullptr;
   d.stats = out;
   d.u_new = out + 4;
   d.plant_x = c.plant;
@@ -392,6 +414,15 @@ LaunchShape plain_shape(brmppi_ctx* ctx, const brmppi_problem& p) {
   const size_t noise = (size_t)normals_per_step(p) * p.T * round_up(p.S, 256) * sizeof(float);
   if (variant_pre(s.variant) && noise > kMaxNoiseBytes) s.variant = 0;
   return s;
+}
+
+// dynamic LDS of the fused epilogue for a plain launch, 0 when the tiles are
+// not whole units or do not fit (k_reduce then reduces from HBM)
+size_t fused_lds(const brmppi_problem& p, const LaunchShape& sh) {
+  const uint32_t per_tile = sh.block / (uint32_t)variant_lanes(sh.variant);
+  if (per_tile % kUnit) return 0;
+  const size_t b = fused_lds_bytes(per_tile, p.T, (p.S + kWChunk - 1) / kWChunk);
+  return b <= kFusedLdsMax ? b : 0;
 }
 
 ScratchLayout plain_layout(const brmppi_problem& p, const LaunchShape& sh) {
@@ -451,36 +482,29 @@ int enqueue_noise(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, cons
 }
 
 // rollout + weights + reduce (+ plant) of one instance whose normals, if the
-// shape reads them, are already in its noise buffer (or ordered before on st)
+// shape reads them, are already in its noise buffer (or ordered before on st);
+// lds > 0: the rollout reduces its own tiles (fused epilogue, no k_reduce)
 int enqueue_rollout_reduce(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
-                           const ScratchLayout& L, const LaunchShape& sh) {
+                           const ScratchLayout& L, const LaunchShape& sh, size_t lds) {
   const int bucket = bucket_for(p.n_obs, p.flags);
   const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
   const uint32_t grid = (p.S + per_tile - 1) / per_tile;
   int rc = timed(ctx, st, 0, [&] {
-    return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
+    return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, lds, st);
   });
-  if (rc) return rc;
+  if (rc || lds) return rc;
   const uint32_t nr = L.n_wchunk * L.n_rgroup;
   return timed(ctx, st, 1, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
 }
 
+// (noise +) rollout + weights + reduce (+ plant) of one instance
 int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
-                   const ScratchLayout& L, const LaunchShape& sh) {
-  const int bucket = bucket_for(p.n_obs, p.flags);
-  const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
-  const uint32_t grid = (p.S + per_tile - 1) / per_tile;
+                   const ScratchLayout& L, const LaunchShape& sh, size_t lds) {
   int rc;
   if (variant_pre(sh.variant)) {
     if ((rc = enqueue_noise(ctx, st, d_desc, p, L))) return rc;
   }
-  rc = timed(ctx, st, 0, [&] {
-    return launch_rollout(bucket, sh.variant, d_desc, nullptr, grid, nullptr, grid, sh.block, st);
-  });
-  if (rc) return rc;
-  // weights, reduction, update, shift and (on request) the plant step
-  const uint32_t nr = L.n_wchunk * L.n_rgroup;
-  return timed(ctx, st, 1, [&] { return launch_reduce(d_desc, nullptr, nr, nullptr, nr, st); });
+  return enqueue_rollout_reduce(ctx, st, d_desc, p, L, sh, lds);
 }
 
 int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
@@ -503,7 +527,8 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   const LaunchShape sh = plain_shape(ctx, *p);
   const ScratchLayout L = plain_layout(*p, sh);
   // device: [scratch | input block]
-  const InputBlock IB = input_block(p->T, p->u_nom != nullptr);
+  const size_t lds = fused_lds(*p, sh);
+  const InputBlock IB = input_block(p->T, p->u_nom != nullptr, L.n_wchunk);
   const size_t in_off = L.bytes;
   if ((rc = ensure_scratch(ctx, in_off + round_up(IB.bytes, 256)))) return rc;
   char* base = ctx->scratch.ptr;
@@ -518,11 +543,12 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   float* pin_out = reinterpret_cast<float*>(pin + round_up(IB.bytes, 256));
 
   fill_desc(*h_desc, *p, c, L, base, 0, reinterpret_cast<const float*>(base + in_off + IB.unom),
-            reinterpret_cast<uint32_t*>(base + in_off + IB.counter), reinterpret_cast<float*>(base + L.off_out));
+            reinterpret_cast<uint32_t*>(base + in_off + IB.counter), reinterpret_cast<float*>(base + L.off_out),
+            lds > 0, out->useq_out != nullptr);
   std::memset(pin + IB.counter, 0, IB.unom - IB.counter);
   if (p->u_nom) std::memcpy(pin + IB.unom, p->u_nom, sizeof(float) * 3 * p->T);
   HIPCHK(hipMemcpyAsync(d_desc, h_desc, IB.bytes, hipMemcpyHostToDevice, s));
-  if ((rc = enqueue_single(ctx, s, d_desc, *p, L, sh))) return rc;
+  if ((rc = enqueue_single(ctx, s, d_desc, *p, L, sh, lds))) return rc;
   HIPCHK(hipMemcpyAsync(pin_out, base + L.off_out, out_floats * sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   collect_timing(ctx);
@@ -659,7 +685,7 @@ int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& 
   const uint32_t nt = (uint32_t)bp.tiles.size(), nr = (uint32_t)bp.ritems.size();
   const uint32_t g_roll = persistent_grid(ctx, bp.bucket, bp.block, nt);
   const uint32_t g_r = std::max<uint32_t>(1, std::min<uint32_t>(nr, (uint32_t)ctx->n_cu * 8));
-  auto L0 = [&] { return launch_rollout(bp.bucket, 0, descs, tiles, nt, ctr, g_roll, bp.block, st); };
+  auto L0 = [&] { return launch_rollout(bp.bucket, 0, descs, tiles, nt, ctr, g_roll, bp.block, 0, st); };
   auto L1 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
   int rc;
   if (timing) {
@@ -801,12 +827,13 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   }
   const LaunchShape sh = plain_shape(ctx, p);
   const ScratchLayout L = plain_layout(p, sh);
-  // device: [scratch | descriptors of every update | counter | nominal | logs];
-  // descriptors, counter and nominal sequence travel in one upload
+  const size_t lds = fused_lds(p, sh);
+  // device: [scratch | descriptors of every update | counters | nominal | logs];
+  // descriptors, counters and nominal sequence travel in one upload
   const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
   const size_t in_off = L.bytes;
   const size_t ctr_rel = desc_bytes * n_up;
-  const size_t unom_rel = ctr_rel + 256;
+  const size_t unom_rel = ctr_rel + counter_bytes(L.n_wchunk);
   const size_t in_bytes = unom_rel + (p.u_nom ? sizeof(float) * 3 * p.T : 0);
   const size_t log_off = in_off + round_up(in_bytes, 256);
   const size_t log_end = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
@@ -836,10 +863,10 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   for (uint32_t k = 0; k < n_up; ++k) {
     SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
     // only the first update reads the caller's sequence; later ones the shifted result
-    fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out);
+    fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out, lds > 0, false);
     if (pre) hd->noise = reinterpret_cast<float*>(base + noise_off + (k % C) * noise_bytes);
   }
-  std::memset(pin + ctr_rel, 0, 256);
+  std::memset(pin + ctr_rel, 0, unom_rel - ctr_rel);
   if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, sizeof(float) * 3 * p.T);
   char* pin_x = pin + round_up(in_bytes, 256);
   if (!resume) {
@@ -855,14 +882,14 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   for (uint32_t k = 0; k < n_up; ++k) {
     const SolveDesc* dd = desc_at(k);
     if (!pre) {
-      if ((rc = enqueue_single(ctx, s, dd, p, L, sh))) return rc;   // includes the plant step
+      if ((rc = enqueue_single(ctx, s, dd, p, L, sh, lds))) return rc;   // includes the plant step
     } else {
       if (k % C == 0) {
         const uint32_t cnt = std::min(C, n_up - k);
         rc = timed(ctx, s, 4, [&] { return launch_noise(dd, desc_bytes, cnt, p.S, p.T, L.n_normals, s); });
         if (rc) return rc;
       }
-      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh))) return rc;
+      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh, lds))) return rc;
     }
     if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
     if (u_applied)
@@ -1426,7 +1453,8 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       const ScratchLayout L = scratch_layout(S, T, K);
       const size_t off_desc = L.bytes, off_path = off_desc + round_up(sizeof(SolveDesc), 256);
       const size_t off_unom = off_path + round_up(sizeof(float4) * n_path, 256);
-      const size_t need = off_unom + round_up(sizeof(float) * 3 * T, 256);
+      const size_t off_ctr = off_unom + round_up(sizeof(float) * 3 * T, 256);
+      const size_t need = off_ctr + counter_bytes(L.n_wchunk);
       if (ensure_scratch(ctx, need) != 0) break;   // larger classes do not fit this arena
       char* base = ctx->scratch.ptr;
       SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + off_desc);
@@ -1434,6 +1462,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       float* d_unom = reinterpret_cast<float*>(base + off_unom);
       HIPCHK(hipMemcpy(d_path, path.data(), sizeof(float4) * n_path, hipMemcpyHostToDevice));
       HIPCHK(hipMemset(d_unom, 0, sizeof(float) * 3 * T));
+      HIPCHK(hipMemset(base + off_ctr, 0, counter_bytes(L.n_wchunk)));   // not captured in a graph
       SolveDesc h;
       std::memset(&h, 0, sizeof(h));
       h.prm = P;
@@ -1451,6 +1480,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       h.n_wchunk = L.n_wchunk;
       h.n_rgroup = L.n_rgroup;
       h.n_ritems = L.n_wchunk * L.n_rgroup;
+      h.n_units = L.n_units;
       h.n_normals = K;
       h.path = d_path;
       h.u_nom_in = d_unom;
@@ -1458,6 +1488,14 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       h.u_star = reinterpret_cast<float*>(base + L.off_ustar);
       h.J = reinterpret_cast<float*>(base + L.off_J);
       h.noise = reinterpret_cast<float*>(base + L.off_noise);
+      h.wpart = reinterpret_cast<float4*>(base + L.off_wpart);
+      h.rpart = reinterpret_cast<float*>(base + L.off_rpart);
+      h.upart = reinterpret_cast<float4*>(base + L.off_upart);
+      h.urow = reinterpret_cast<float*>(base + L.off_urow);
+      h.counter = reinterpret_cast<uint32_t*>(base + off_ctr);
+      h.gctr = h.counter + kCtrStride;
+      h.stats = reinterpret_cast<float*>(base + L.off_out);
+      h.u_new = h.stats + 4;
       for (int o = 0; o < bucket; ++o) {
         h.obs[o].cx = 2.0f + 1.5f * o;
         h.obs[o].cy = (o % 2) ? 2.5f : -2.5f;
@@ -1470,17 +1508,30 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       LaunchShape best = ctx->shape[bi][sc];
       float best_ms = 1e30f, best_v0 = 1e30f;
       uint32_t best_v0_block = ctx->batch_block[bi];
-      std::string times;             // [block, variant, ms per noise + rollout] of every candidate
+      std::string times;             // [block, variant, ms per noise + rollout + reduce] of every candidate
       for (int variant = 0; variant <= kMaxVariant; ++variant) {
         if (bucket == 0 && variant > 1) continue;
         const uint32_t lanes = (uint32_t)variant_lanes(variant);
         for (uint32_t block : {64u, 128u, 256u}) {
           const uint32_t per_tile = block / lanes;
           const uint32_t grid = (S + per_tile - 1) / per_tile;
+          // time what a plain solve would run: fused epilogue where the tiles
+          // are whole units, else the rollout plus k_reduce
+          size_t lds = 0;
+          if (per_tile % kUnit == 0) {
+            lds = fused_lds_bytes(per_tile, T, L.n_wchunk);
+            if (lds > kFusedLdsMax) lds = 0;
+          }
+          h.fused = lds ? 1u : 0u;
+          h.ustar_global = lds ? 0u : 1u;
+          HIPCHK(hipMemcpy(d_desc, &h, sizeof(h), hipMemcpyHostToDevice));
+          const uint32_t nr = L.n_wchunk * L.n_rgroup;
           auto run = [&]() -> hipError_t {
             hipError_t e = hipSuccess;
             if (variant_pre(variant)) e = launch_noise(d_desc, 0, 1, S, T, K, s);
-            if (e == hipSuccess) e = launch_rollout(bucket, variant, d_desc, nullptr, grid, nullptr, grid, block, s);
+            if (e == hipSuccess)
+              e = launch_rollout(bucket, variant, d_desc, nullptr, grid, nullptr, grid, block, lds, s);
+            if (e == hipSuccess && !lds) e = launch_reduce(d_desc, nullptr, nr, nullptr, nr, s);
             return e;
           };
           HIPCHK(run());
