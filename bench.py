@@ -258,15 +258,24 @@ def extras(args, B, W, ctx, prob):
 
     note("paper shape")
     # ---- the paper's own problem shape: H = 120, 5000 rollouts, 8 obstacles ----
+    # with the two MPPI baselines of the paper's comparison (plain MPPI and MPPI
+    # with a collision penalty) timed the same way
     pp = W.config2().copy(S=5000, T=120, params=W.make_params(0.04), u_nom=np.zeros((120, 3), np.float32))
-    ctx.set_path(2, pp.path, pp.ds)
-    lat = []
-    for k in range(40):
-        _, st, _ = B.brmppi_solve(h, B.ProblemBuffers(pp, controller=2, with_nominal=(k == 0), seed=k))
-        if k >= 5:
-            lat.append(st["latency_us"] * 1e-3)
-    res["paper_shape"] = {"S": 5000, "T": 120, "n_obs": 8, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-                          "paper_ms": 9.9, "paper_hw": "unnamed single GPU, JAX"}
+    ps = {}
+    for name, flags, paper_ms in (("br_mppi", 0, 9.9), ("mppi", W.FLAG_GUIDANCE_OFF, 3.2),
+                                  ("mppi_col", W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY, 13.0)):
+        q = pp.copy(flags=flags)
+        ctx.set_path(2, q.path, q.ds)
+        lat = []
+        for k in range(40):
+            _, st, _ = B.brmppi_solve(h, B.ProblemBuffers(q, controller=2, with_nominal=(k == 0), seed=k))
+            if k >= 5:
+                lat.append(st["latency_us"] * 1e-3)
+        ps[name] = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "paper_ms": paper_ms}
+    res["paper_shape"] = {"S": 5000, "T": 120, "n_obs": 8, **ps["br_mppi"], "paper_hw": "unnamed single GPU, JAX",
+                          "baselines": {"mppi": ps["mppi"], "mppi_col": ps["mppi_col"]},
+                          "note": "paper_ms: forward-parking times of the paper's comparison (its table of "
+                                  "MPPI, MPPI + collision cost, BR-MPPI)"}
     return res
 
 

@@ -65,6 +65,11 @@ extern "C" {
 #define BRMPPI_ADVANCE_PLANT 8u   /* after the update, advance the resident plant state by
                                      the first averaged input (jerk and steer rate clamped
                                      to [j_lo, j_hi], [w_lo, w_hi]) with eq. (6) in FP64 */
+#define BRMPPI_COLLISION_PENALTY 16u /* the paper's second baseline (Sec. V), whose form it
+                                     does not give: w_col * sum_o max(0, -h_o(x, t))^2,
+                                     h_o the e = 2 obstacle function of eq. (16) at the
+                                     current state, added to every stage cost and to the
+                                     terminal cost; usually with BRMPPI_GUIDANCE_OFF */
 
 /* ---- context flags ------------------------------------------------------ */
 #define BRMPPI_CTX_PROFILE 1u     /* time every kernel of the blocking calls with HIP events */
@@ -97,13 +102,16 @@ typedef struct {
  *                              [alpha_lo, alpha_hi] on the next rate
  *  sampling (Sec. III-B):     sigma_j, sigma_w, sigma_nu (input noise),
  *                              sigma_a (auxiliary-input noise)
- *  guard:                     h_eps (|hhat| floor in each row) */
+ *  guard:                     h_eps (|hhat| floor in each row)
+ *  baseline (Sec. V):         w_col, weight of the collision penalty added to the
+ *                              stage and terminal costs under BRMPPI_COLLISION_PENALTY */
 typedef struct {
   float Ts, l1, lh, l2, dtheta_max, kappa, r_disc;
   float Qc, Ql, Qth1, Qth2, R_j, R_w, mu, nu_bar;
   float W_j, W_w, W_a, rho, j_lo, j_hi, w_lo, w_hi;
   float alpha0, alpha_lo, alpha_hi, sigma_j, sigma_w, sigma_nu, sigma_a;
   float h_eps;
+  float w_col;   /* weight of the collision-penalty baseline (BRMPPI_COLLISION_PENALTY) */
 } brmppi_params;
 
 /* Obstacle (Sec. IV-C, eq. (16)): centre (cx, cy) at t = 0, semi-axes (mx, my),
@@ -126,7 +134,7 @@ typedef struct {
   uint64_t seed;              /* Philox key */
   uint32_t instance;          /* Philox counter word 3 */
   uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT |
-                                 BRMPPI_ADVANCE_PLANT */
+                                 BRMPPI_ADVANCE_PLANT | BRMPPI_COLLISION_PENALTY */
   const brmppi_params* params;/* required */
 } brmppi_problem;
 

@@ -443,6 +443,20 @@ double orc_stage_cost(const double x[8], const double u[3], const double* path, 
          p->mu * prog * prog;
 }
 
+/* Collision-penalty baseline (Sec. V, the second MPPI baseline; the paper   */
+/* gives no formula).  READING: w_col * sum_o max(0, -h_o(x, t))^2 with h_o   */
+/* the e = 2 obstacle function of eq. (16) at the current state and time,    */
+/* added to the stage cost of every step and to the terminal cost.           */
+double orc_collision_penalty(const double x[8], double t, const orc_obstacle* obs, int n_obs, const orc_params* p) {
+  double pen = 0.0;
+  for (int o = 0; o < n_obs; ++o) {
+    orc_barrier B;
+    orc_obstacle_barrier(x, t, &obs[o], p, &B);
+    if (B.h < 0.0) pen += B.h * B.h;
+  }
+  return p->w_col * pen;
+}
+
 /* READING: r_N (eq. (7)) is the tracking part of eq. (13) at the final state */
 double orc_terminal_cost(const double x[8], const double* path, int n, double ds, const orc_params* p) {
   return tracking_terms(x, path, n, ds, p);
@@ -497,6 +511,7 @@ double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const
       u[1] = zs[1];
     }
     J += orc_stage_cost(x, u, pr->path, pr->n_path, pr->ds, p);
+    if (pr->flags & ORC_COLLISION_PENALTY) J += orc_collision_penalty(x, t, pr->obs, pr->n_obs, p);
     if (useq) memcpy(useq + 3 * tau, u, sizeof(u));
     double xn[8];
     orc_step(x, u, p, xn);
@@ -507,6 +522,8 @@ double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const
     if (alphas) memcpy(alphas + (size_t)nc * tau, alpha, sizeof(double) * nc);
   }
   J += orc_terminal_cost(x, pr->path, pr->n_path, pr->ds, p);
+  if (pr->flags & ORC_COLLISION_PENALTY)
+    J += orc_collision_penalty(x, pr->t0 + pr->T * p->Ts, pr->obs, pr->n_obs, p);
   free(alpha); free(e); free(hraw); free(hh); free(G); free(Lf); free(b); free(zd); free(zs);
   if (!isfinite(J)) J = INFINITY;
   return J;

@@ -22,12 +22,13 @@ typedef struct {
   double W_j, W_w, W_a, rho, j_lo, j_hi, w_lo, w_hi;
   double alpha0, alpha_lo, alpha_hi, sigma_j, sigma_w, sigma_nu, sigma_a;
   double h_eps;
+  double w_col;                /* collision-penalty weight (baseline flag only) */
 } orc_params;
 
 /* obstacle: centre, semi-axes, orientation, exponent, constant velocity */
 typedef struct { double cx, cy, mx, my, heading, e, vx, vy; } orc_obstacle;
 
-enum { ORC_GUIDANCE_OFF = 1, ORC_HITCH_OFF = 2 };
+enum { ORC_GUIDANCE_OFF = 1, ORC_HITCH_OFF = 2, ORC_COLLISION_PENALTY = 16 };
 
 typedef struct {
   int S, T;
@@ -75,6 +76,7 @@ double orc_wrap(double a);
 double orc_stage_cost(const double x[8], const double u[3], const double* path, int n, double ds,
                       const orc_params* p);
 double orc_terminal_cost(const double x[8], const double* path, int n, double ds, const orc_params* p);
+double orc_collision_penalty(const double x[8], double t, const orc_obstacle* obs, int n_obs, const orc_params* p);
 
 double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const double* eps,
                    double* useq, double* traj, double* alphas);

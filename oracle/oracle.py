@@ -20,11 +20,12 @@ PARAM_FIELDS = (
     "Qc", "Ql", "Qth1", "Qth2", "R_j", "R_w", "mu", "nu_bar",
     "W_j", "W_w", "W_a", "rho", "j_lo", "j_hi", "w_lo", "w_hi",
     "alpha0", "alpha_lo", "alpha_hi", "sigma_j", "sigma_w", "sigma_nu", "sigma_a",
-    "h_eps",
+    "h_eps", "w_col",
 )
 
 GUIDANCE_OFF = 1
 HITCH_OFF = 2
+COLLISION_PENALTY = 16
 
 
 class Params(C.Structure):
@@ -91,6 +92,8 @@ def lib():
         L.orc_stage_cost.restype = D
         L.orc_terminal_cost.argtypes = [P, P, I, D, C.POINTER(Params)]
         L.orc_terminal_cost.restype = D
+        L.orc_collision_penalty.argtypes = [P, D, C.POINTER(Obstacle), I, C.POINTER(Params)]
+        L.orc_collision_penalty.restype = D
         L.orc_rollout.argtypes = [C.POINTER(ProblemC), C.POINTER(Params), U32, P, P, P, P]
         L.orc_rollout.restype = D
         L.orc_rollout_samples.argtypes = [C.POINTER(ProblemC), C.POINTER(Params), C.POINTER(U32), I, I, P, P]
@@ -316,6 +319,15 @@ def terminal_cost(x, path, ds, params):
     path = np.ascontiguousarray(np.asarray(path, dtype=np.float64).reshape(-1))
     P = params_struct(params)
     return lib().orc_terminal_cost(_dp(x), _dp(path), path.size // 4, float(ds), C.byref(P))
+
+
+def collision_penalty(x, t, obstacles, params):
+    """w_col * sum_o max(0, -h_o(x, t))^2 (the collision-penalty baseline)"""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    obs = np.ascontiguousarray(np.asarray(obstacles, dtype=np.float64).reshape(-1, 8))
+    arr = (Obstacle * max(len(obs), 1))(*[obstacle_struct(o) for o in obs])
+    P = params_struct(params)
+    return lib().orc_collision_penalty(_dp(x), float(t), arr, len(obs), C.byref(P))
 
 
 def weights(J, lam):

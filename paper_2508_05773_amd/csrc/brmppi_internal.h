@@ -21,6 +21,7 @@ constexpr uint32_t kCtrStride = 32;          // completion counters one 128-B li
 constexpr int kPathWin = 1024;    // waypoints staged in LDS per tile
 constexpr int kPathBack = 64;     // of which before the start progress
 constexpr int kMaxBlock = 256;    // rollout block size bound (launch_bounds)
+constexpr int kNoisePrefetch = 2;   // steps of normals loaded ahead of their use
 
 // Per-update descriptor read by every kernel (device memory).
 struct alignas(16) SolveDesc {

@@ -301,6 +301,22 @@ __device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t t
   return d.noise + ((size_t)tau * d.n_normals + k) * d.S_pad;
 }
 
+// Collision-penalty baseline (the paper's second MPPI baseline, Sec. V; its
+// form is not given): sum_o max(0, -h_o)^2 with h_o = d'Q d - 1 the e = 2
+// obstacle function of eq. (16) at the current position and time, in
+// obstacle order (every lane of a group sums all obstacles).
+__device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, int n_obs, float px, float py,
+                                               float t) {
+  float pen = 0.0f;
+  for (int o = 0; o < n_obs; ++o) {
+    const ObsL ob = sobs[o];
+    const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
+    const float h = dx * (ob.q11 * dx + ob.q12 * dy) + dy * (ob.q12 * dx + ob.q22 * dy) - 1.0f;
+    pen += (h < 0.0f) ? h * h : 0.0f;
+  }
+  return pen;
+}
+
 // sine and cosine of the four angles a step needs (th1, th1 - th2, delta and
 // the reference heading), one sincos per lane for G >= 4, then broadcast
 struct StepTrig {
@@ -381,6 +397,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const bool hitch = !(d.flags & BRMPPI_HITCH_OFF);
   // an unguided instance may share a guided launch: the flag is honoured here
   const bool guided = GUIDED && !(d.flags & BRMPPI_GUIDANCE_OFF);
+  const bool penalty = (d.flags & BRMPPI_COLLISION_PENALTY) != 0;
   const int nb = guided ? (5 + n_obs + 3) / 4 : 1;
   const float ox = x0[0], oy = x0[1];
   const float4* __restrict__ gpath = d.path;
@@ -412,24 +429,30 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   float* __restrict__ ustar = d.u_star;
   const float* __restrict__ unom = d.u_nom_in;
 
-  // precomputed normals of the next step (prefetched one step ahead)
-  float nx_in[3], nx_h[NH], nx_o[NSL];
-  auto load_normals = [&](uint32_t tau) {
+  // precomputed normals of the next PF steps (a register queue: slot 0 is
+  // the current step, loads run PF steps ahead of their use)
+  constexpr int PF = PRE ? kNoisePrefetch : 1;
+  float nx_in[PF][3], nx_h[PF][NH], nx_o[PF][NSL];
+  auto load_normals = [&](uint32_t tau, int q) {
     if constexpr (PRE) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) nx_in[k] = noise_row(d, tau, k)[s];
+      for (int k = 0; k < 3; ++k) nx_in[q][k] = noise_row(d, tau, k)[s];
       if (guided) {
 #pragma unroll
-        for (int k = 0; k < NH; ++k) nx_h[k] = noise_row(d, tau, 3 + hk0 + k)[s];
+        for (int k = 0; k < NH; ++k) nx_h[q][k] = noise_row(d, tau, 3 + hk0 + k)[s];
 #pragma unroll
         for (int j = 0; j < NSL; ++j) {
           const int o = g + G * j;
-          nx_o[j] = (o < n_obs) ? noise_row(d, tau, 5 + o)[s] : 0.0f;
+          nx_o[q][j] = (o < n_obs) ? noise_row(d, tau, 5 + o)[s] : 0.0f;
         }
       }
     }
   };
-  if constexpr (PRE) load_normals(0);
+  if constexpr (PRE) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if ((uint32_t)q < d.T) load_normals((uint32_t)q, q);
+  }
 
   for (uint32_t tau = 0; tau < d.T; ++tau) {
     // --- noise: normals 0..2 perturb the inputs, 3 and 4 the hitch rows'
@@ -437,12 +460,21 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     float e_in[3], e_h[NH], e_o[NSL];
     if constexpr (PRE) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) e_in[k] = nx_in[k];
+      for (int k = 0; k < 3; ++k) e_in[k] = nx_in[0][k];
 #pragma unroll
-      for (int k = 0; k < NH; ++k) e_h[k] = nx_h[k];
+      for (int k = 0; k < NH; ++k) e_h[k] = nx_h[0][k];
 #pragma unroll
-      for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[j];
-      if (tau + 1 < d.T) load_normals(tau + 1);
+      for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[0][j];
+#pragma unroll
+      for (int q = 0; q + 1 < PF; ++q) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nx_in[q][k] = nx_in[q + 1][k];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) nx_h[q][k] = nx_h[q + 1][k];
+#pragma unroll
+        for (int j = 0; j < NSL; ++j) nx_o[q][j] = nx_o[q + 1][j];
+      }
+      if (tau + PF < d.T) load_normals(tau + PF, PF - 1);
     } else {
       float eps[4 * NBMAX];
 #pragma unroll
@@ -555,8 +587,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 
     // --- stage cost r(x_tau, u*_tau, psi_tau), eq. (13) ---
     const float prog = P.nu_bar - unu;
-    const float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
-                     P.R_w * uw * uw + P.mu * prog * prog;
+    float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
+               P.R_w * uw * uw + P.mu * prog * prog;
+    if (penalty) rc += P.w_col * collision_pen(sobs, n_obs, px, py, d.t0 + (float)tau * Ts);
     J += (double)rc;
 
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
@@ -591,7 +624,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     dl = ndl;
   }
   const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
-  J += (double)tracking_cost(P, rf, px, py, th1, th2);
+  float rN = tracking_cost(P, rf, px, py, th1, th2);
+  if (penalty) rN += P.w_col * collision_pen(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
+  J += (double)rN;
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
   if (store) {

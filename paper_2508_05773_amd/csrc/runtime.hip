@@ -323,7 +323,8 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (p->n_obs > BRMPPI_MAX_OBS) return fail(BRMPPI_EINVAL, "too many obstacles");
   if (p->n_obs > 0 && !p->obs) return fail(BRMPPI_EINVAL, "obstacles pointer is NULL");
   if (!p->params) return fail(BRMPPI_EINVAL, "params pointer is NULL");
-  if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT))
+  if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT |
+                   BRMPPI_COLLISION_PENALTY))
     return fail(BRMPPI_EINVAL, "unknown flags");
   if ((p->flags & BRMPPI_ADVANCE_PLANT) && !(p->flags & BRMPPI_X0_RESIDENT))
     return fail(BRMPPI_EINVAL, "BRMPPI_ADVANCE_PLANT needs BRMPPI_X0_RESIDENT");

@@ -29,12 +29,13 @@ PARAM_FIELDS = (
     "Qc", "Ql", "Qth1", "Qth2", "R_j", "R_w", "mu", "nu_bar",
     "W_j", "W_w", "W_a", "rho", "j_lo", "j_hi", "w_lo", "w_hi",
     "alpha0", "alpha_lo", "alpha_hi", "sigma_j", "sigma_w", "sigma_nu", "sigma_a",
-    "h_eps",
+    "h_eps", "w_col",
 )
 
 # flags (same bit values as the C-ABI header)
 FLAG_GUIDANCE_OFF = 1   # plain MPPI: sampled inputs are applied unprojected
 FLAG_HITCH_OFF = 2      # no hitch-angle rows
+FLAG_COLLISION_PENALTY = 16  # baseline: w_col * sum_o max(0, -h_o)^2 added to the cost
 
 
 def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
@@ -47,7 +48,10 @@ def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
     width), alpha0 = 0.5 with soft bounds [-1, 1], aux-input noise 0.2, the
     projection weight W equal to the inverse sampling covariance, rho = 0.1,
     contouring weights Qc = Ql = 2, heading weights 1, effort 0.05, progress
-    weight 0.5 toward a maximum progress rate of 2 m/s.
+    weight 0.5 toward a maximum progress rate of 2 m/s.  The collision-penalty
+    baseline (a flag) weighs max(0, -h_o)^2 by w_col = 1000, so that a sample
+    reaching an obstacle's centre (h = -1) costs far more than any tracking
+    error of the horizon.
     """
     sj, sw, sn = (float(s) for s in sigma)
     sa = 0.2
@@ -57,7 +61,7 @@ def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
         W_j=1.0 / sj ** 2, W_w=1.0 / sw ** 2, W_a=1.0 / sa ** 2, rho=0.1,
         j_lo=-2.0, j_hi=2.0, w_lo=-0.9, w_hi=0.9,
         alpha0=0.5, alpha_lo=-1.0, alpha_hi=1.0,
-        sigma_j=sj, sigma_w=sw, sigma_nu=sn, sigma_a=sa, h_eps=1e-5,
+        sigma_j=sj, sigma_w=sw, sigma_nu=sn, sigma_a=sa, h_eps=1e-5, w_col=1000.0,
     )
     p.update(over)
     # round every value to float32 so both sides see identical numbers

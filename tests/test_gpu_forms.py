@@ -162,7 +162,9 @@ def test_closed_loop_matches_plain_and_oracle_plant(ctx):
         assert np.allclose(x_cl[k + 1], want, rtol=1e-14, atol=1e-14), k
 
 
-@pytest.mark.parametrize("n_obs,flags", [(7, 0), (2, 0), (13, W.FLAG_HITCH_OFF), (29, 0), (5, W.FLAG_GUIDANCE_OFF)])
+@pytest.mark.parametrize("n_obs,flags", [(7, 0), (2, 0), (13, W.FLAG_HITCH_OFF), (29, 0), (5, W.FLAG_GUIDANCE_OFF),
+                                         (7, W.FLAG_COLLISION_PENALTY),
+                                         (4, W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY)])
 def test_launch_shapes_bitwise_identical(ctx, n_obs, flags):
     """every (block size, lanes per sample, noise source) gives the same bits:
     costs, applied sequences and the update"""

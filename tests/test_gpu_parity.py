@@ -112,6 +112,22 @@ def test_flags(ctx, flags):
     compare(prob, g, o, f"flags{flags}")
 
 
+@pytest.mark.parametrize("flags", [W.FLAG_COLLISION_PENALTY | W.FLAG_GUIDANCE_OFF, W.FLAG_COLLISION_PENALTY])
+def test_collision_penalty_baseline(ctx, flags):
+    """the collision-penalty baseline (with and without guidance) against the
+    oracle, with an obstacle placed just ahead of the start"""
+    from oracle import oracle as O
+    prob = W.random_small(21, S=700, T=17, n_obs=5)
+    obs = prob.obstacles.copy()
+    obs[0, 0], obs[0, 1] = prob.x0[0] + 1.0, prob.x0[1] + 0.3
+    prob = prob.copy(obstacles=obs, flags=flags)
+    g = run_gpu(ctx, prob, controller=23)
+    o = O.solve(prob, nthreads=NTHREADS)
+    compare(prob, g, o, f"penalty flags={flags}")
+    plain = O.solve(prob.copy(flags=flags & ~W.FLAG_COLLISION_PENALTY), nthreads=NTHREADS)
+    assert np.count_nonzero(o["J"] > plain["J"]) > 0        # the penalty was active
+
+
 @pytest.mark.parametrize("S,T,n_obs", [(1, 1, 0), (1, 5, 3), (63, 2, 32), (257, 1, 1), (1025, 3, 16)])
 def test_edge_shapes(ctx, S, T, n_obs):
     from oracle import oracle as O

@@ -137,3 +137,64 @@ def test_cbf_linearisation_second_order(orc):
             gaps.append(Bn["hhat"] - (B["hhat"] + Lf + g @ u[:2]))
         ratios.append(gaps[0] / gaps[1])
     assert 3.5 < np.median(ratios) < 4.5
+
+
+def _ellipse_point(o, r_disc, f, axis):
+    """point at fraction f of the inflated semi-axis `axis` (0: along the
+    heading, 1: across it) of obstacle row o = (cx, cy, mx, my, heading, e, vx, vy)"""
+    cx, cy, mx, my, hd = o[0], o[1], o[2], o[3], o[4]
+    if axis == 0:
+        a = mx + r_disc
+        return cx + f * a * math.cos(hd), cy + f * a * math.sin(hd)
+    a = my + r_disc
+    return cx - f * a * math.sin(hd), cy + f * a * math.cos(hd)
+
+
+@pytest.mark.parametrize("hd", [0.0, 0.7, -2.3])
+def test_collision_penalty_geometry(orc, hd):
+    """The collision-penalty baseline: at an obstacle's centre h = -1 (penalty
+    w_col); at a fraction f of an inflated semi-axis h = f^2 - 1 (penalty
+    w_col (1 - f^2)^2); on or outside the boundary 0; obstacles add up; a moving
+    obstacle's centre is c + v t."""
+    prm = _prm()
+    w = prm["w_col"]
+    r = prm["r_disc"]
+    o = np.array([3.0, -1.0, 2.5, 1.0, hd, 2.0, 0.0, 0.0])
+    x = np.zeros(8)
+    x[0], x[1] = o[0], o[1]
+    assert orc.collision_penalty(x, 0.0, [o], prm) == pytest.approx(w, rel=1e-12)
+    for axis in (0, 1):
+        for f in (0.0, 0.3, 0.9):
+            x[0], x[1] = _ellipse_point(o, r, f, axis)
+            assert orc.collision_penalty(x, 0.0, [o], prm) == pytest.approx(w * (1 - f * f) ** 2, rel=1e-9, abs=1e-9)
+        for f in (1.0, 1.5):
+            x[0], x[1] = _ellipse_point(o, r, f, axis)
+            assert orc.collision_penalty(x, 0.0, [o], prm) == pytest.approx(0.0, abs=1e-9)
+    # two copies of the same obstacle count twice
+    x[0], x[1] = _ellipse_point(o, r, 0.5, 1)
+    assert orc.collision_penalty(x, 0.0, [o, o], prm) == pytest.approx(2 * w * 0.75 ** 2, rel=1e-9)
+    # moving: at time t the centre is c + v t
+    om = o.copy()
+    om[6], om[7] = 1.5, -0.5
+    x[0], x[1] = o[0] + 1.5 * 2.0, o[1] - 0.5 * 2.0
+    assert orc.collision_penalty(x, 2.0, [om], prm) == pytest.approx(w, rel=1e-12)
+    assert orc.collision_penalty(x, 0.0, [om], prm) < w
+
+
+def test_collision_penalty_in_rollout(orc):
+    """Without guidance the trajectory does not depend on the cost, so the
+    penalty flag adds exactly the penalty of every visited state x_0..x_T (at
+    t0 + tau Ts) to a sample's cost."""
+    p = W.random_small(5, S=8, T=12, n_obs=3)
+    # put an obstacle on the start so that the penalty is not zero
+    obs = p.obstacles.copy()
+    obs[0, 0], obs[0, 1] = p.x0[0] + 0.5, p.x0[1]
+    p = p.copy(obstacles=obs, flags=W.FLAG_GUIDANCE_OFF, t0=0.25)
+    pp = p.copy(flags=W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY)
+    for s in range(4):
+        J0, u0, x0, _ = orc.rollout(p, s)
+        J1, u1, x1, _ = orc.rollout(pp, s)
+        assert np.array_equal(u0, u1) and np.array_equal(x0, x1)
+        pen = sum(orc.collision_penalty(x1[k], p.t0 + k * p.params["Ts"], obs, p.params) for k in range(p.T + 1))
+        assert pen > 0
+        assert J1 - J0 == pytest.approx(pen, rel=1e-9)
