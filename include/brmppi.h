@@ -70,6 +70,14 @@ extern "C" {
                                      h_o the e = 2 obstacle function of eq. (16) at the
                                      current state, added to every stage cost and to the
                                      terminal cost; usually with BRMPPI_GUIDANCE_OFF */
+#define BRMPPI_HITCH_QP 32u       /* hitch-angle stabiliser (Sec. IV-D, eq. (19)) before the
+                                     plant step (needs BRMPPI_ADVANCE_PLANT): the applied
+                                     (j, omega) minimise ||u - U_new[0]||^2 over the input box
+                                     with Q_h = diag(qh_j, qh_w), subject to the discrete CBF
+                                     condition Lf + g u >= -alpha_h hhat of both hitch rows
+                                     (the first-order expanded barrier of the rollouts);
+                                     solved exactly in FP64 on the device; when no input
+                                     satisfies it, the box-clipped U_new[0] is applied */
 
 /* ---- context flags ------------------------------------------------------ */
 #define BRMPPI_CTX_PROFILE 1u     /* time every kernel of the blocking calls with HIP events */
@@ -104,7 +112,9 @@ typedef struct {
  *                              sigma_a (auxiliary-input noise)
  *  guard:                     h_eps (|hhat| floor in each row)
  *  baseline (Sec. V):         w_col, weight of the collision penalty added to the
- *                              stage and terminal costs under BRMPPI_COLLISION_PENALTY */
+ *                              stage and terminal costs under BRMPPI_COLLISION_PENALTY
+ *  stabiliser, eq. (19):      qh_j, qh_w (diagonal Q_h), alpha_h (class-K rate of the
+ *                              hitch rows) of the CBF-QP under BRMPPI_HITCH_QP */
 typedef struct {
   float Ts, l1, lh, l2, dtheta_max, kappa, r_disc;
   float Qc, Ql, Qth1, Qth2, R_j, R_w, mu, nu_bar;
@@ -112,6 +122,7 @@ typedef struct {
   float alpha0, alpha_lo, alpha_hi, sigma_j, sigma_w, sigma_nu, sigma_a;
   float h_eps;
   float w_col;   /* weight of the collision-penalty baseline (BRMPPI_COLLISION_PENALTY) */
+  float qh_j, qh_w, alpha_h;  /* hitch-angle stabiliser (BRMPPI_HITCH_QP): Q_h, class-K rate */
 } brmppi_params;
 
 /* Obstacle (Sec. IV-C, eq. (16)): centre (cx, cy) at t = 0, semi-axes (mx, my),
@@ -134,7 +145,8 @@ typedef struct {
   uint64_t seed;              /* Philox key */
   uint32_t instance;          /* Philox counter word 3 */
   uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT |
-                                 BRMPPI_ADVANCE_PLANT | BRMPPI_COLLISION_PENALTY */
+                                 BRMPPI_ADVANCE_PLANT | BRMPPI_COLLISION_PENALTY |
+                                 BRMPPI_HITCH_QP */
   const brmppi_params* params;/* required */
 } brmppi_problem;
 

@@ -604,6 +604,113 @@ int orc_solve(const orc_problem* pr, const orc_params* p, int nthreads, const do
 /* Closed-loop plant for the reverse-parking workload: the first averaged input,
  * jerk and steer rate clamped to the actuator bounds of Sec. V, applied with
  * eq. (6); the virtual progress state advances by Ts nu. */
+/* ------------------------------------------------------------------------ */
+/* Hitch-angle stabiliser (Sec. IV-D, eq. (19)): u* = argmin over the input  */
+/* box of ||u - u_ref||^2_{Q_h} subject to the discrete CBF condition of the */
+/* hitch barrier, on (j, omega).  READINGS: the barrier has relative degree  */
+/* 2 in (j, omega), so the condition uses the same first-order expansion as  */
+/* the rollout rows, hhat = h + Ts hdot, one row per sign of the hitch angle;*/
+/* the class-K term carries the standard sign, Lf + g u >= -alpha_h hhat;    */
+/* U is the hard input box [j_lo, j_hi] x [w_lo, w_hi].  Solved exactly by    */
+/* enumerating the active sets of at most two of the six constraints and     */
+/* keeping the KKT point (primal and dual feasible).  If no input satisfies   */
+/* the constraints, the reference clipped to the box is returned (status 1). */
+/* ------------------------------------------------------------------------ */
+int orc_hitch_qp(const double x[8], const double uref[2], const orc_params* p, double u_out[2]) {
+  double A[6][2], c[6];
+  double f[8];
+  orc_drift(x, p, f);
+  int n = 0;
+  for (int sgn = 1; sgn >= -1; sgn -= 2, ++n) {
+    orc_barrier B;
+    orc_hitch_barrier(x, sgn, p, &B);
+    double hraw, hh, G2[2], Lf;
+    row_from_barrier(&B, f, p, &hraw, &hh, G2, &Lf);
+    A[n][0] = G2[0];
+    A[n][1] = G2[1];
+    c[n] = -p->alpha_h * hraw - Lf;
+  }
+  const double box[4][3] = {{1, 0, p->j_lo}, {-1, 0, -p->j_hi}, {0, 1, p->w_lo}, {0, -1, -p->w_hi}};
+  for (int k = 0; k < 4; ++k, ++n) {
+    A[n][0] = box[k][0];
+    A[n][1] = box[k][1];
+    c[n] = box[k][2];
+  }
+  const double q[2] = {p->qh_j, p->qh_w};
+  double best = INFINITY, bu[2] = {0, 0};
+  /* active set of size 0 */
+  int cand = 0;
+  double U[1 + 6 + 15][2], L[1 + 6 + 15][2];
+  int act[1 + 6 + 15][2], nact[1 + 6 + 15];
+  U[cand][0] = uref[0];
+  U[cand][1] = uref[1];
+  nact[cand++] = 0;
+  /* size 1: u = uref + Q^-1 a lam, a'u = c */
+  for (int i = 0; i < n; ++i) {
+    const double aQa = A[i][0] * A[i][0] / q[0] + A[i][1] * A[i][1] / q[1];
+    if (!(aQa > 0.0)) continue;
+    const double lam = (c[i] - (A[i][0] * uref[0] + A[i][1] * uref[1])) / aQa;
+    U[cand][0] = uref[0] + A[i][0] / q[0] * lam;
+    U[cand][1] = uref[1] + A[i][1] / q[1] * lam;
+    L[cand][0] = lam;
+    act[cand][0] = i;
+    nact[cand++] = 1;
+  }
+  /* size 2: M lam = c_S - A_S uref, M_ik = a_i' Q^-1 a_k */
+  for (int i = 0; i < n; ++i) {
+    for (int k = i + 1; k < n; ++k) {
+      const double m00 = A[i][0] * A[i][0] / q[0] + A[i][1] * A[i][1] / q[1];
+      const double m01 = A[i][0] * A[k][0] / q[0] + A[i][1] * A[k][1] / q[1];
+      const double m11 = A[k][0] * A[k][0] / q[0] + A[k][1] * A[k][1] / q[1];
+      const double det = m00 * m11 - m01 * m01;
+      if (!(fabs(det) > 1e-14 * (m00 * m11 + 1e-300))) continue;
+      const double r0 = c[i] - (A[i][0] * uref[0] + A[i][1] * uref[1]);
+      const double r1 = c[k] - (A[k][0] * uref[0] + A[k][1] * uref[1]);
+      const double l0 = (m11 * r0 - m01 * r1) / det, l1 = (m00 * r1 - m01 * r0) / det;
+      U[cand][0] = uref[0] + (A[i][0] * l0 + A[k][0] * l1) / q[0];
+      U[cand][1] = uref[1] + (A[i][1] * l0 + A[k][1] * l1) / q[1];
+      L[cand][0] = l0;
+      L[cand][1] = l1;
+      act[cand][0] = i;
+      act[cand][1] = k;
+      nact[cand++] = 2;
+    }
+  }
+  for (int z = 0; z < cand; ++z) {
+    int ok = 1;
+    for (int j = 0; j < nact[z]; ++j)
+      if (L[z][j] < -1e-12) ok = 0;                      /* dual feasibility */
+    for (int i = 0; i < n && ok; ++i) {
+      const double r = A[i][0] * U[z][0] + A[i][1] * U[z][1] - c[i];
+      const double scale = fabs(c[i]) + fabs(A[i][0] * U[z][0]) + fabs(A[i][1] * U[z][1]) + 1e-300;
+      if (r < -1e-10 * scale) ok = 0;                    /* primal feasibility */
+    }
+    if (!ok) continue;
+    const double obj = q[0] * (U[z][0] - uref[0]) * (U[z][0] - uref[0]) + q[1] * (U[z][1] - uref[1]) * (U[z][1] - uref[1]);
+    if (obj < best) {
+      best = obj;
+      bu[0] = U[z][0];
+      bu[1] = U[z][1];
+    }
+  }
+  if (best < INFINITY) {
+    u_out[0] = bu[0];
+    u_out[1] = bu[1];
+    return 0;
+  }
+  u_out[0] = fmin(fmax(uref[0], p->j_lo), p->j_hi);
+  u_out[1] = fmin(fmax(uref[1], p->w_lo), p->w_hi);
+  return 1;
+}
+
+/* closed-loop plant step with the stabiliser applied to the averaged input */
+void orc_plant_step_qp(const double x[8], const double U0[3], const orc_params* p, double xn[8]) {
+  double u[3];
+  orc_hitch_qp(x, U0, p, u);
+  u[2] = U0[2];
+  orc_step(x, u, p, xn);
+}
+
 void orc_plant_step(const double x[8], const double U0[3], const orc_params* p, double xn[8]) {
   double u[3] = {U0[0], U0[1], U0[2]};
   if (u[0] < p->j_lo) u[0] = p->j_lo;

@@ -23,6 +23,7 @@ typedef struct {
   double alpha0, alpha_lo, alpha_hi, sigma_j, sigma_w, sigma_nu, sigma_a;
   double h_eps;
   double w_col;                /* collision-penalty weight (baseline flag only) */
+  double qh_j, qh_w, alpha_h;  /* hitch-angle stabiliser QP, eq. (19): Q_h, class-K rate */
 } orc_params;
 
 /* obstacle: centre, semi-axes, orientation, exponent, constant velocity */
@@ -76,6 +77,8 @@ double orc_wrap(double a);
 double orc_stage_cost(const double x[8], const double u[3], const double* path, int n, double ds,
                       const orc_params* p);
 double orc_terminal_cost(const double x[8], const double* path, int n, double ds, const orc_params* p);
+int orc_hitch_qp(const double x[8], const double uref[2], const orc_params* p, double u_out[2]);
+void orc_plant_step_qp(const double x[8], const double U0[3], const orc_params* p, double xn[8]);
 double orc_collision_penalty(const double x[8], double t, const orc_obstacle* obs, int n_obs, const orc_params* p);
 
 double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const double* eps,

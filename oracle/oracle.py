@@ -20,12 +20,13 @@ PARAM_FIELDS = (
     "Qc", "Ql", "Qth1", "Qth2", "R_j", "R_w", "mu", "nu_bar",
     "W_j", "W_w", "W_a", "rho", "j_lo", "j_hi", "w_lo", "w_hi",
     "alpha0", "alpha_lo", "alpha_hi", "sigma_j", "sigma_w", "sigma_nu", "sigma_a",
-    "h_eps", "w_col",
+    "h_eps", "w_col", "qh_j", "qh_w", "alpha_h",
 )
 
 GUIDANCE_OFF = 1
 HITCH_OFF = 2
 COLLISION_PENALTY = 16
+HITCH_QP = 32
 
 
 class Params(C.Structure):
@@ -93,6 +94,9 @@ def lib():
         L.orc_terminal_cost.argtypes = [P, P, I, D, C.POINTER(Params)]
         L.orc_terminal_cost.restype = D
         L.orc_collision_penalty.argtypes = [P, D, C.POINTER(Obstacle), I, C.POINTER(Params)]
+        L.orc_hitch_qp.argtypes = [P, P, C.POINTER(Params), P]
+        L.orc_hitch_qp.restype = I
+        L.orc_plant_step_qp.argtypes = [P, P, C.POINTER(Params), P]
         L.orc_collision_penalty.restype = D
         L.orc_rollout.argtypes = [C.POINTER(ProblemC), C.POINTER(Params), U32, P, P, P, P]
         L.orc_rollout.restype = D
@@ -328,6 +332,26 @@ def collision_penalty(x, t, obstacles, params):
     arr = (Obstacle * max(len(obs), 1))(*[obstacle_struct(o) for o in obs])
     P = params_struct(params)
     return lib().orc_collision_penalty(_dp(x), float(t), arr, len(obs), C.byref(P))
+
+
+def hitch_qp(x, uref, params):
+    """hitch-angle stabiliser (eq. (19)) at state x for the reference (j, omega):
+    returns (u*, status) with status 1 when the constraints are infeasible"""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    ur = np.ascontiguousarray(np.asarray(uref, dtype=np.float64)[:2])
+    out = np.zeros(2)
+    P = params_struct(params)
+    st = lib().orc_hitch_qp(_dp(x), _dp(ur), C.byref(P), _dp(out))
+    return out, st
+
+
+def plant_step_qp(x, U0, params):
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    u = np.ascontiguousarray(np.asarray(U0, dtype=np.float64))
+    xn = np.zeros(8)
+    P = params_struct(params)
+    lib().orc_plant_step_qp(_dp(x), _dp(u), C.byref(P), _dp(xn))
+    return xn
 
 
 def weights(J, lam):

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "brmppi.h")
 # return codes / flags (include/brmppi.h)
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EAGAIN, ENONFINITE, ENOTICKET, EDEVICE, ETIMEDOUT, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
-GUIDANCE_OFF, HITCH_OFF, X0_RESIDENT, ADVANCE_PLANT, COLLISION_PENALTY = 1, 2, 4, 8, 16
+GUIDANCE_OFF, HITCH_OFF, X0_RESIDENT, ADVANCE_PLANT, COLLISION_PENALTY, HITCH_QP = 1, 2, 4, 8, 16, 32
 CTX_PROFILE, CTX_PROFILE_ROLLOUT = 1, 2
 MAX_OBS, MAX_T = 32, 512
 
@@ -29,7 +29,7 @@ PARAM_FIELDS = (
     "Qc", "Ql", "Qth1", "Qth2", "R_j", "R_w", "mu", "nu_bar",
     "W_j", "W_w", "W_a", "rho", "j_lo", "j_hi", "w_lo", "w_hi",
     "alpha0", "alpha_lo", "alpha_hi", "sigma_j", "sigma_w", "sigma_nu", "sigma_a",
-    "h_eps", "w_col",
+    "h_eps", "w_col", "qh_j", "qh_w", "alpha_h",
 )
 
 

@@ -734,6 +734,77 @@ __device__ __forceinline__ void plant_prep(const SolveDesc& d, double* s_plant) 
     s_plant[2 * t + 1] = cs;
   }
 }
+// Hitch-angle stabiliser (Sec. IV-D, eq. (19)) in FP64: (j, w) <- argmin of
+// q_j (j - j_ref)^2 + q_w (w - w_ref)^2 over the input box subject to
+// Lf + g u >= -alpha_h hhat for both hitch rows (the first-order expanded
+// barrier of the rollouts).  The optimum of this strictly convex 2-D problem
+// is the reference, the projection onto one constraint line, or a vertex of
+// two: every candidate is formed and the feasible one with the least cost
+// kept.  No feasible input: the reference clipped to the box.
+__device__ bool hitch_qp(const brmppi_params& P, const double x[8], const double* s_plant, double& j, double& w) {
+  const double Ts = P.Ts, l1 = P.l1, l2 = P.l2;
+  const double v = x[2], a = x[3], phi = x[4] - x[5];
+  const double sp = s_plant[4], cp = s_plant[5];
+  const double tn = s_plant[2] / s_plant[3], sec2 = 1.0 + tn * tn;
+  const double ch = (double)P.lh / l1, kd = tn / l1;
+  const double Aw2 = sp - ch * cp * tn;
+  const double D = v / l2 * Aw2 - v * kd;
+  const double D_v = Aw2 / l2 - kd;
+  const double D_phi = v / l2 * (cp + ch * sp * tn);
+  const double D_dl = -v * sec2 * (ch * cp / l2 + 1.0 / l1);
+  double A[6][2], c[6];
+  for (int k = 0; k < 2; ++k) {
+    const double sg = k == 0 ? 1.0 : -1.0;
+    const double h = (double)P.dtheta_max - (double)P.kappa * v + sg * phi;
+    const double hd = -(double)P.kappa * a - sg * D;
+    const double hv = -(double)P.kappa - sg * Ts * D_v;
+    const double Lf = Ts * (hv * a - sg * (1.0 - Ts * D_phi) * D);
+    A[k][0] = -(double)P.kappa * Ts * Ts;
+    A[k][1] = -sg * Ts * Ts * D_dl;
+    c[k] = -(double)P.alpha_h * (h + Ts * hd) - Lf;
+  }
+  A[2][0] = 1.0;  A[2][1] = 0.0;  c[2] = P.j_lo;
+  A[3][0] = -1.0; A[3][1] = 0.0;  c[3] = -(double)P.j_hi;
+  A[4][0] = 0.0;  A[4][1] = 1.0;  c[4] = P.w_lo;
+  A[5][0] = 0.0;  A[5][1] = -1.0; c[5] = -(double)P.w_hi;
+  const double q0 = P.qh_j, q1 = P.qh_w;
+  const double r0 = j, r1 = w;
+  double best = INFINITY, b0 = 0.0, b1 = 0.0;
+  auto consider = [&](double u0, double u1) {
+    for (int i = 0; i < 6; ++i) {
+      const double lhs = A[i][0] * u0 + A[i][1] * u1;
+      const double scale = fabs(c[i]) + fabs(A[i][0] * u0) + fabs(A[i][1] * u1) + 1e-300;
+      if (lhs - c[i] < -1e-10 * scale) return;
+    }
+    const double e0 = u0 - r0, e1 = u1 - r1;
+    const double obj = q0 * e0 * e0 + q1 * e1 * e1;
+    if (obj < best) {
+      best = obj;
+      b0 = u0;
+      b1 = u1;
+    }
+  };
+  consider(r0, r1);
+  for (int i = 0; i < 6; ++i) {
+    const double aQa = A[i][0] * A[i][0] / q0 + A[i][1] * A[i][1] / q1;
+    if (!(aQa > 0.0)) continue;
+    const double lam = (c[i] - (A[i][0] * r0 + A[i][1] * r1)) / aQa;
+    consider(r0 + A[i][0] / q0 * lam, r1 + A[i][1] / q1 * lam);
+  }
+  for (int i = 0; i < 6; ++i) {
+    for (int k = i + 1; k < 6; ++k) {
+      const double det = A[i][0] * A[k][1] - A[i][1] * A[k][0];
+      const double nrm = fabs(A[i][0] * A[k][1]) + fabs(A[i][1] * A[k][0]);
+      if (!(fabs(det) > 1e-14 * nrm)) continue;
+      consider((c[i] * A[k][1] - c[k] * A[i][1]) / det, (A[i][0] * c[k] - A[k][0] * c[i]) / det);
+    }
+  }
+  if (!(best < INFINITY)) return false;
+  j = b0;
+  w = b1;
+  return true;
+}
+
 // second half, one thread, after a barrier
 __device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s_plant) {
   const brmppi_params& P = d.prm;
@@ -741,8 +812,11 @@ __device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s
   for (int k = 0; k < 8; ++k) x[k] = s_plant[6 + k];
   double j = s_plant[14], w = s_plant[15];
   const double nu = s_plant[16];
-  j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
-  w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
+  const bool stabilised = (d.flags & BRMPPI_HITCH_QP) && hitch_qp(P, x, s_plant, j, w);
+  if (!stabilised) {   // hard input bounds on the applied input
+    j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
+    w = fmin(fmax(w, (double)P.w_lo), (double)P.w_hi);
+  }
   const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
   const double v = x[2], a = x[3];
   const double s1 = s_plant[0], c1 = s_plant[1];

@@ -324,8 +324,10 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (p->n_obs > 0 && !p->obs) return fail(BRMPPI_EINVAL, "obstacles pointer is NULL");
   if (!p->params) return fail(BRMPPI_EINVAL, "params pointer is NULL");
   if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT |
-                   BRMPPI_COLLISION_PENALTY))
+                   BRMPPI_COLLISION_PENALTY | BRMPPI_HITCH_QP))
     return fail(BRMPPI_EINVAL, "unknown flags");
+  if ((p->flags & BRMPPI_HITCH_QP) && !(p->flags & BRMPPI_ADVANCE_PLANT))
+    return fail(BRMPPI_EINVAL, "BRMPPI_HITCH_QP acts on the plant step (BRMPPI_ADVANCE_PLANT)");
   if ((p->flags & BRMPPI_ADVANCE_PLANT) && !(p->flags & BRMPPI_X0_RESIDENT))
     return fail(BRMPPI_EINVAL, "BRMPPI_ADVANCE_PLANT needs BRMPPI_X0_RESIDENT");
   const brmppi_params& P = *p->params;
@@ -336,6 +338,8 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
       P.W_w < 0 || P.W_a < 0)
     return fail(BRMPPI_EINVAL, "projection weights must be >= 0 with W + rho > 0");
   if (!(p->lambda > 0) || !std::isfinite(p->lambda)) return fail(BRMPPI_EINVAL, "lambda must be positive");
+  if ((p->flags & BRMPPI_HITCH_QP) && (!(P.qh_j > 0) || !(P.qh_w > 0) || !(P.alpha_h > 0)))
+    return fail(BRMPPI_EINVAL, "BRMPPI_HITCH_QP needs qh_j, qh_w and alpha_h positive");
   if (!std::isfinite(p->t0)) return fail(BRMPPI_EINVAL, "t0 must be finite");
   for (uint32_t i = 0; i < p->n_obs; ++i) {
     const brmppi_obstacle& o = p->obs[i];

@@ -29,13 +29,14 @@ PARAM_FIELDS = (
     "Qc", "Ql", "Qth1", "Qth2", "R_j", "R_w", "mu", "nu_bar",
     "W_j", "W_w", "W_a", "rho", "j_lo", "j_hi", "w_lo", "w_hi",
     "alpha0", "alpha_lo", "alpha_hi", "sigma_j", "sigma_w", "sigma_nu", "sigma_a",
-    "h_eps", "w_col",
+    "h_eps", "w_col", "qh_j", "qh_w", "alpha_h",
 )
 
 # flags (same bit values as the C-ABI header)
 FLAG_GUIDANCE_OFF = 1   # plain MPPI: sampled inputs are applied unprojected
 FLAG_HITCH_OFF = 2      # no hitch-angle rows
 FLAG_COLLISION_PENALTY = 16  # baseline: w_col * sum_o max(0, -h_o)^2 added to the cost
+FLAG_HITCH_QP = 32      # closed loop: hitch-angle stabiliser QP on the applied input
 
 
 def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
@@ -51,7 +52,9 @@ def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
     weight 0.5 toward a maximum progress rate of 2 m/s.  The collision-penalty
     baseline (a flag) weighs max(0, -h_o)^2 by w_col = 1000, so that a sample
     reaching an obstacle's centre (h = -1) costs far more than any tracking
-    error of the horizon.
+    error of the horizon.  The hitch-angle stabiliser QP weighs the deviation
+    from the averaged input by the inverse sampling covariance (as W does) and
+    uses the class-K rate alpha_h = 0.5.
     """
     sj, sw, sn = (float(s) for s in sigma)
     sa = 0.2
@@ -62,6 +65,7 @@ def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
         j_lo=-2.0, j_hi=2.0, w_lo=-0.9, w_hi=0.9,
         alpha0=0.5, alpha_lo=-1.0, alpha_hi=1.0,
         sigma_j=sj, sigma_w=sw, sigma_nu=sn, sigma_a=sa, h_eps=1e-5, w_col=1000.0,
+        qh_j=1.0 / sj ** 2, qh_w=1.0 / sw ** 2, alpha_h=0.5,
     )
     p.update(over)
     # round every value to float32 so both sides see identical numbers

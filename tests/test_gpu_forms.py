@@ -233,3 +233,47 @@ def test_invalid_arguments_leave_state(ctx):
     assert e.value.code in (B.ESTATE,)
     # the warm start of 407 is unchanged by the failed calls
     assert np.array_equal(B.brmppi_get_nominal(ctx.h, 407, p.T), np.concatenate([good[1:], good[-1:]]))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 4])
+def test_hitch_stabiliser_plant_step(ctx, seed):
+    """The device hitch-angle QP (eq. (19)) against the oracle's, at plant
+    states where the hitch row binds.  With zero sampling noise and guidance
+    off every sample applies the nominal sequence, so U_new[0] is exactly the
+    chosen reference; the stabilised plant step must match the oracle's (FP64,
+    different exact methods: candidate enumeration vs active-set KKT)."""
+    from oracle import oracle as O
+    from tests.hitch_qp_cases import binding_state
+    base = W.random_small(95, S=64, T=4, n_obs=2)
+    prm = W.make_params(0.05, dtheta_max=0.35)
+    prm.update(sigma_j=0.0, sigma_w=0.0, sigma_nu=0.0, sigma_a=0.0)
+    x, uref = binding_state(O, prm, np.random.default_rng(seed))
+    # few significant bits: the weighted average of identical sequences is then exact
+    uref = np.round(uref * 1024.0) / 1024.0
+    uq, st = O.hitch_qp(x, uref, prm)
+    assert st == 0 and not np.allclose(uq, uref)
+    u_nom = np.zeros((base.T, 3), np.float32)
+    u_nom[:, 0], u_nom[:, 1], u_nom[:, 2] = uref[0], uref[1], 0.5
+    uref32 = u_nom[0].astype(np.float64)
+    p = base.copy(params=prm, u_nom=u_nom, flags=W.FLAG_GUIDANCE_OFF)
+    cid = 410 + seed
+    ctx.set_path(cid, p.path, p.ds)
+    for flags, plant in ((B.HITCH_QP, O.plant_step_qp), (0, O.plant_step)):
+        B.brmppi_set_state(ctx.h, cid, x)
+        pb = B.ProblemBuffers(p, controller=cid, flags=p.flags | B.X0_RESIDENT | B.ADVANCE_PLANT | flags)
+        u, _, _ = B.brmppi_solve(ctx.h, pb)
+        assert np.array_equal(u[0], u_nom[0])                 # U_new[0] is the reference
+        xn = B.brmppi_get_state(ctx.h, cid)
+        want = plant(x, uref32, prm)
+        log(f"  hitch QP seed {seed} flags {flags}: max |dx| {np.abs(xn - want).max():.2e}")
+        assert np.allclose(xn, want, rtol=1e-12, atol=1e-13), (flags, xn, want)
+    # the stabiliser changed the applied input
+    assert not np.allclose(O.plant_step_qp(x, uref32, prm), O.plant_step(x, uref32, prm))
+
+
+def test_hitch_stabiliser_needs_plant_step(ctx):
+    p = W.random_small(96, S=64, T=4, n_obs=1)
+    ctx.set_path(415, p.path, p.ds)
+    with pytest.raises(B.BrmppiError) as e:
+        B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=415, flags=B.HITCH_QP))
+    assert e.value.code == B.EINVAL
