@@ -115,13 +115,17 @@ void orc_step(const double x[8], const double u[3], const orc_params* p, double 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Obstacle barrier, eqs. (16) and (17) with e = 2.                           */
-/* h = d'Qd - 1, d = p - p_o(t), Q = R' diag((mx+r)^-2, (my+r)^-2) R, where   */
-/* R rotates world into the obstacle frame (eq. (16) primes).  READING: the  */
-/* obstacle moves with constant velocity (Assumption 2), p_o(t) = c + v_o t.  */
-/* hd and hdd are the first and second time derivatives of h along the drift */
-/* (relative degree 3: neither depends on the input), and                     */
-/* hhat = h + Ts hd + Ts^2/2 hdd (eq. (17)).                                   */
+/* Obstacle barrier, eqs. (16) and (17), exponent e in {2, 4}.                */
+/* h = sum_i (d'_i / (m_i + r))^e - 1 with d' = R d the obstacle-frame       */
+/* offsets (eq. (16) primes), d = p - p_o(t).  READING: the obstacle moves   */
+/* with constant velocity (Assumption 2), p_o(t) = c + v_o t.  hd and hdd    */
+/* are the first and second time derivatives of h along the drift (relative  */
+/* degree 3: neither depends on the input), and                              */
+/* hhat = h + Ts hd + Ts^2/2 hdd (eq. (17)).  Written in the world frame with */
+/* the gradient G = R' phi1, Hessian H = R' diag(phi2) R and third           */
+/* derivative T3[u, w] = R' (phi3 (R u)(R w)) of h in the position, where    */
+/* phi_k is the k-th derivative of y -> (y / (m_i + r))^e per axis; for e = 2 */
+/* H = 2Q and T3 = 0.                                                         */
 /* ------------------------------------------------------------------------ */
 
 static void mat2_vec(const double Q[2][2], const double v[2], double out[2]) {
@@ -129,19 +133,20 @@ static void mat2_vec(const double Q[2][2], const double v[2], double out[2]) {
   out[1] = Q[1][0] * v[0] + Q[1][1] * v[1];
 }
 static double dot2(const double a[2], const double b[2]) { return a[0] * b[0] + a[1] * b[1]; }
+static double ipow(double y, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= y;
+  return r;
+}
 
 void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, const orc_params* p,
                           orc_barrier* out) {
   const double v = x[2], a = x[3], th1 = x[4], dl = x[6];
   const double Ts = p->Ts;
-  /* shape matrix */
-  const double ax = o->mx + p->r_disc, ay = o->my + p->r_disc;
+  const int e = (int)o->e;
   const double co = cos(o->heading), so = sin(o->heading);
-  const double R[2][2] = {{co, so}, {-so, co}};
-  const double D[2] = {1.0 / (ax * ax), 1.0 / (ay * ay)};
-  double Q[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) Q[i][j] = R[0][i] * D[0] * R[0][j] + R[1][i] * D[1] * R[1][j];
+  const double R[2][2] = {{co, so}, {-so, co}};          /* world -> obstacle frame */
+  const double rho[2] = {1.0 / (o->mx + p->r_disc), 1.0 / (o->my + p->r_disc)};
 
   const double vo[2] = {o->vx, o->vy};
   const double d[2] = {x[0] - (o->cx + o->vx * t), x[1] - (o->cy + o->vy * t)};
@@ -153,17 +158,33 @@ void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, co
   const double dd[2] = {v * e1[0] - vo[0], v * e1[1] - vo[1]};
   const double ddd[2] = {a * e1[0] + v * v * kd * e2[0], a * e1[1] + v * v * kd * e2[1]};
 
-  double Qd[2], Qdd[2], Qddd[2], Qe1[2], Qe2[2], Qvo[2];
-  mat2_vec(Q, d, Qd);
-  mat2_vec(Q, dd, Qdd);
-  mat2_vec(Q, ddd, Qddd);
-  mat2_vec(Q, e1, Qe1);
-  mat2_vec(Q, e2, Qe2);
-  mat2_vec(Q, vo, Qvo);
+  /* per-axis derivatives of phi in the obstacle frame */
+  double dp[2], f0 = -1.0, f1[2], f2[2], f3[2];
+  mat2_vec(R, d, dp);
+  for (int i = 0; i < 2; ++i) {
+    const double ri = ipow(rho[i], e);
+    f0 += ri * ipow(dp[i], e);
+    f1[i] = e * ri * ipow(dp[i], e - 1);
+    f2[i] = e * (e - 1) * ri * ipow(dp[i], e - 2);
+    f3[i] = (e >= 3) ? e * (e - 1) * (e - 2) * ri * ipow(dp[i], e - 3) : 0.0;
+  }
+  /* world-frame gradient, Hessian and third-derivative contraction T3[dd, dd] */
+  double G[2], H[2][2];
+  G[0] = R[0][0] * f1[0] + R[1][0] * f1[1];
+  G[1] = R[0][1] * f1[0] + R[1][1] * f1[1];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) H[i][j] = R[0][i] * f2[0] * R[0][j] + R[1][i] * f2[1] * R[1][j];
+  double Rdd[2], T3dd[2];
+  mat2_vec(R, dd, Rdd);
+  T3dd[0] = R[0][0] * f3[0] * Rdd[0] * Rdd[0] + R[1][0] * f3[1] * Rdd[1] * Rdd[1];
+  T3dd[1] = R[0][1] * f3[0] * Rdd[0] * Rdd[0] + R[1][1] * f3[1] * Rdd[1] * Rdd[1];
+  double Hdd[2], Hddd[2];
+  mat2_vec(H, dd, Hdd);
+  mat2_vec(H, ddd, Hddd);
 
-  const double h = dot2(d, Qd) - 1.0;
-  const double hd = 2.0 * dot2(d, Qdd);
-  const double hdd = 2.0 * dot2(dd, Qdd) + 2.0 * dot2(d, Qddd);
+  const double h = f0;
+  const double hd = dot2(G, dd);
+  const double hdd = dot2(dd, Hdd) + dot2(G, ddd);
   out->h = h;
   out->hd = hd;
   out->hdd = hdd;
@@ -171,34 +192,30 @@ void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, co
 
   /* partial derivatives of h, hd, hdd (chain rule, term by term) */
   double gh[8] = {0}, ghd[8] = {0}, ghdd[8] = {0};
-  double th = 0, thd = 0, thdd = 0; /* time partials */
-  /* h = d'Qd */
-  gh[0] = 2.0 * Qd[0];
-  gh[1] = 2.0 * Qd[1];
-  th = -2.0 * dot2(vo, Qd);
-  /* hd = 2 d'Q dd;  dd depends on v, th1 */
-  ghd[0] = 2.0 * Qdd[0];
-  ghd[1] = 2.0 * Qdd[1];
-  ghd[2] = 2.0 * dot2(d, Qe1);                 /* d dd / dv = e1 */
-  ghd[4] = 2.0 * v * dot2(d, Qe2);             /* d dd / dth1 = v e2 */
-  thd = -2.0 * dot2(vo, Qdd);
-  /* hdd = 2 dd'Q dd + 2 d'Q ddd;  ddd depends on v, a, th1, delta */
-  ghdd[0] = 2.0 * Qddd[0];
-  ghdd[1] = 2.0 * Qddd[1];
+  double th, thd, thdd; /* time partials */
+  /* h(d) */
+  gh[0] = G[0];
+  gh[1] = G[1];
+  th = -dot2(vo, G);
+  /* hd = G(d) . dd;  dd depends on v, th1 */
+  ghd[0] = Hdd[0];
+  ghd[1] = Hdd[1];
+  ghd[2] = dot2(G, e1);                        /* d dd / dv = e1 */
+  ghd[4] = v * dot2(G, e2);                    /* d dd / dth1 = v e2 */
+  thd = -dot2(vo, Hdd);
+  /* hdd = dd' H(d) dd + G(d) . ddd;  ddd depends on v, a, th1, delta */
+  ghdd[0] = T3dd[0] + Hddd[0];
+  ghdd[1] = T3dd[1] + Hddd[1];
   {
     const double dddv[2] = {2.0 * v * kd * e2[0], 2.0 * v * kd * e2[1]};
     const double dddth[2] = {a * e2[0] - v * v * kd * e1[0], a * e2[1] - v * v * kd * e1[1]};
     const double ddddl[2] = {v * v * dkd * e2[0], v * v * dkd * e2[1]};
-    double Qdddv[2], Qdddth[2], Qddddl[2];
-    mat2_vec(Q, dddv, Qdddv);
-    mat2_vec(Q, dddth, Qdddth);
-    mat2_vec(Q, ddddl, Qddddl);
-    ghdd[2] = 4.0 * dot2(e1, Qdd) + 2.0 * dot2(d, Qdddv);
-    ghdd[3] = 2.0 * dot2(d, Qe1);
-    ghdd[4] = 4.0 * v * dot2(e2, Qdd) + 2.0 * dot2(d, Qdddth);
-    ghdd[6] = 2.0 * dot2(d, Qddddl);
+    ghdd[2] = 2.0 * dot2(e1, Hdd) + dot2(G, dddv);
+    ghdd[3] = dot2(G, e1);
+    ghdd[4] = 2.0 * v * dot2(e2, Hdd) + dot2(G, dddth);
+    ghdd[6] = dot2(G, ddddl);
   }
-  thdd = -2.0 * dot2(vo, Qddd);
+  thdd = -(T3dd[0] * vo[0] + T3dd[1] * vo[1]) - dot2(vo, Hddd);
 
   for (int i = 0; i < 8; ++i) out->grad[i] = gh[i] + Ts * ghd[i] + 0.5 * Ts * Ts * ghdd[i];
   out->dt = th + Ts * thd + 0.5 * Ts * Ts * thdd;

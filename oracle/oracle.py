@@ -132,8 +132,8 @@ class OracleProblem:
         self.u_nom = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1)[: 3 * self.T])
         self.path = np.ascontiguousarray(np.asarray(prob.path, dtype=np.float64).reshape(-1))
         obs = np.asarray(prob.obstacles, dtype=np.float64).reshape(-1, 8)
-        if obs.shape[0] and np.any(obs[:, 5] != 2.0):
-            raise ValueError("the oracle implements the e = 2 barrier only")
+        if obs.shape[0] and np.any((obs[:, 5] != 2.0) & (obs[:, 5] != 4.0)):
+            raise ValueError("the oracle implements the e = 2 and e = 4 barriers only")
         self.obs = (Obstacle * max(1, obs.shape[0]))(*[obstacle_struct(o) for o in obs])
         self.params = params_struct(prob.params)
         xx = prob.x0 if x0 is None else x0

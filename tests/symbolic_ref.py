@@ -3,7 +3,8 @@ derivatives, used to pin the oracle's hand-written chain rule.
 
 Everything here is derived mechanically from the definitions in the paper:
   - drift f_c and input columns g_c from eq. (6) (continuous time, psi_dot = nu),
-  - the ellipse barrier eq. (16) with e = 2 around a constant-velocity obstacle,
+  - the super-ellipse barrier eq. (16) (exponent e = 2 or 4) around a
+    constant-velocity obstacle,
   - hhat = h + Ts L h + Ts^2/2 L^2 h  (eq. (17)), L the Lie derivative along f_c
     plus the explicit time derivative,
   - the hitch barrier eq. (18) split in two smooth rows, hhat = h + Ts L h,
@@ -30,12 +31,12 @@ def lie(F):
 
 
 @functools.lru_cache(maxsize=None)
-def obstacle_exprs():
+def obstacle_exprs(e=2):
     dx = px - (cx + vx * t)
     dy = py - (cy + vy * t)
     xp = sp.cos(tho) * dx + sp.sin(tho) * dy
     yp = -sp.sin(tho) * dx + sp.cos(tho) * dy
-    h = (xp / (mx + r)) ** 2 + (yp / (my + r)) ** 2 - 1
+    h = (xp / (mx + r)) ** e + (yp / (my + r)) ** e - 1
     hd = lie(h)
     hdd = lie(hd)
     hhat = h + Ts * hd + Ts ** 2 / 2 * hdd
@@ -62,8 +63,8 @@ HITCH_ARGS = list(X) + [Ts, l1, lh, l2, dthmax, kappa]
 
 
 @functools.lru_cache(maxsize=None)
-def obstacle_funcs(module="numpy"):
-    e = obstacle_exprs()
+def obstacle_funcs(module="numpy", exponent=2):
+    e = obstacle_exprs(exponent)
     out = {}
     for k in ("h", "hd", "hdd", "hhat", "Lf", "g0", "g1", "dt"):
         out[k] = sp.lambdify(OBS_ARGS, e[k], module)

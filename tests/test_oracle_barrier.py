@@ -23,18 +23,19 @@ def _rand_state(rng):
     return x
 
 
-def _rand_obs(rng, moving=True):
+def _rand_obs(rng, moving=True, e=2.0):
     return [rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(0.3, 2.5), rng.uniform(0.3, 2.5),
-            rng.uniform(-math.pi, math.pi), 2.0,
+            rng.uniform(-math.pi, math.pi), e,
             rng.uniform(-1.5, 1.5) if moving else 0.0, rng.uniform(-1.5, 1.5) if moving else 0.0]
 
 
-def test_obstacle_barrier_matches_symbolic(orc):
-    F = SR.obstacle_funcs()
-    rng = np.random.default_rng(0)
+@pytest.mark.parametrize("e", [2, 4])
+def test_obstacle_barrier_matches_symbolic(orc, e):
+    F = SR.obstacle_funcs(exponent=e)
+    rng = np.random.default_rng(0 + 10 * e)
     prm = W.make_params(0.05)
     for _ in range(60):
-        x, o, tt = _rand_state(rng), _rand_obs(rng), rng.uniform(0, 3)
+        x, o, tt = _rand_state(rng), _rand_obs(rng, e=float(e)), rng.uniform(0, 3)
         B = orc.obstacle_barrier(x, tt, o, prm)
         args = SR.obstacle_args(x, tt, prm, o)
         for k in ("h", "hd", "hdd", "hhat"):
@@ -60,12 +61,13 @@ def test_hitch_barrier_matches_symbolic(orc, sign):
         assert B["dt"] == 0.0
 
 
-def test_barrier_gradients_finite_difference(orc):
-    rng = np.random.default_rng(2)
+@pytest.mark.parametrize("e", [2, 4])
+def test_barrier_gradients_finite_difference(orc, e):
+    rng = np.random.default_rng(2 + 10 * e)
     prm = W.make_params(0.05)
     eps = 1e-6
     for _ in range(40):
-        x, o, tt = _rand_state(rng), _rand_obs(rng), rng.uniform(0, 3)
+        x, o, tt = _rand_state(rng), _rand_obs(rng, e=float(e)), rng.uniform(0, 3)
         B = orc.obstacle_barrier(x, tt, o, prm)
         for i in range(8):
             xp, xm = x.copy(), x.copy()
@@ -98,13 +100,13 @@ def _rk4_flow(orc, x, prm, dt, n):
     return out
 
 
-@pytest.mark.parametrize("moving", [False, True])
-def test_barrier_time_derivatives_along_flow(orc, moving):
-    rng = np.random.default_rng(3 + moving)
+@pytest.mark.parametrize("moving,e", [(False, 2), (True, 2), (False, 4), (True, 4)])
+def test_barrier_time_derivatives_along_flow(orc, moving, e):
+    rng = np.random.default_rng(3 + moving + 10 * e)
     prm = W.make_params(0.05)
     dt = 1e-3
     for _ in range(10):
-        x, o, t0 = _rand_state(rng), _rand_obs(rng, moving), rng.uniform(0, 2)
+        x, o, t0 = _rand_state(rng), _rand_obs(rng, moving, e=float(e)), rng.uniform(0, 2)
         fwd = _rk4_flow(orc, x, prm, dt, 2)
         bwd = _rk4_flow(orc, x, prm, -dt, 2)
         hs = {}
@@ -125,10 +127,12 @@ def test_barrier_time_derivatives_along_flow(orc, moving):
 def test_rows_match_definition(orc):
     """Lf = Ts (L hhat), g = Ts (d hhat/da, d hhat/d delta), in the order
     hitch(+), hitch(-), obstacles; hh is hhat guarded by h_eps."""
-    Fo = SR.obstacle_funcs()
     Fp, Fm = SR.hitch_funcs(1), SR.hitch_funcs(-1)
     rng = np.random.default_rng(5)
     prob = W.random_small(1, n_obs=4)
+    obs = prob.obstacles.copy()
+    obs[1::2, 5] = 4.0                        # mix e = 2 and e = 4 rows
+    prob = prob.copy(obstacles=obs)
     prm = prob.params
     for _ in range(20):
         x, tt = _rand_state(rng), rng.uniform(0, 2)
@@ -136,6 +140,7 @@ def test_rows_match_definition(orc):
         assert len(hh) == prob.n_obs + 2
         for o_idx, o in enumerate(prob.obstacles):
             i = 2 + o_idx
+            Fo = SR.obstacle_funcs(exponent=int(o[5]))
             args = SR.obstacle_args(x, tt, prm, o)
             assert hraw[i] == pytest.approx(Fo["hhat"](*args), rel=1e-11, abs=1e-12)
             assert Lf[i] == pytest.approx(Fo["Lf"](*args), rel=1e-10, abs=1e-11)

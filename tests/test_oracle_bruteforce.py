@@ -1,5 +1,5 @@
 """End-to-end pin of the oracle: S = 4 samples, T = 3 steps, one moving
-obstacle plus the two hitch rows, injected noise in {-1, 0, 1}, recomputed in
+obstacle (ellipse e = 2 or super-ellipse e = 4) plus the two hitch rows, injected noise in {-1, 0, 1}, recomputed in
 50-digit mpmath from the paper's equations:
   rows from the sympy derivation (symbolic_ref.py), eq. (9);
   the projection written literally as eq. (12) with mpmath matrices;
@@ -53,20 +53,21 @@ def _euler(x, u, P):
             dl + Ts * u[1], psi + Ts * u[2]]
 
 
-def _problem():
+def _problem(e=2.0):
     prm = W.make_params(0.1)
     path, _ = W.path_c1()
     path = path[:120]
     x0 = np.array([0.3, 0.1, 1.2, 0.2, 0.05, 0.02, 0.04, 0.3], np.float32)
-    obs = np.array([[4.5, 1.6, 0.8, 0.5, 0.3, 2.0, -0.4, 0.2]], np.float32)
+    obs = np.array([[4.5, 1.6, 0.8, 0.5, 0.3, e, -0.4, 0.2]], np.float32)
     T = 3
     u_nom = np.array([[0.2, 0.05, 1.0], [-0.1, 0.0, 1.2], [0.0, -0.05, 0.8]], np.float32)
     return W.Problem(S=4, T=T, x0=x0, u_nom=u_nom, obstacles=obs, path=path, ds=0.1, params=prm,
                      lam=0.7, seed=9, instance=1, t0=0.25)
 
 
-def test_bruteforce_s4_t3(orc):
-    p = _problem()
+@pytest.mark.parametrize("e", [2, 4])
+def test_bruteforce_s4_t3(orc, e):
+    p = _problem(float(e))
     P = {k: mp.mpf(v) for k, v in p.params.items()}
     nc = p.n_obs + 2
     K = 5 + p.n_obs          # normals: 3 inputs, hitch(+), hitch(-), obstacle 0
@@ -74,7 +75,7 @@ def test_bruteforce_s4_t3(orc):
     eps = rng.integers(-1, 2, size=(p.S, p.T, K)).astype(np.float64)
     path = [[mp.mpf(float(v)) for v in row] for row in p.path]
     ds = mp.mpf(p.ds)
-    Fo = SR.obstacle_funcs("mpmath")
+    Fo = SR.obstacle_funcs("mpmath", exponent=e)
     Fh = {s: SR.hitch_funcs(s, "mpmath") for s in (1, -1)}
     sig = [P["sigma_j"], P["sigma_w"], P["sigma_nu"]]
 
