@@ -81,10 +81,12 @@ __device__ __forceinline__ float wrap_angle(float x) { return x - kTwoPi * rintf
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Obstacle staged in LDS: centre relative to the tile origin, velocity, shape
-// matrix Q = R' diag((mx+r)^-2, (my+r)^-2) R of eq. (16) with e = 2.
+// Obstacle staged in LDS: centre relative to the tile origin, velocity; for
+// e = 2 the shape matrix Q = R' diag((mx+r)^-2, (my+r)^-2) R of eq. (16), for
+// e = 4 (e4 = 1) the rotation (co, so) into the obstacle frame and the
+// per-axis coefficients k = (m+r)^-4.
 struct ObsL {
-  float cx, cy, vx, vy, q11, q12, q22, pad;
+  float cx, cy, vx, vy, q11, q12, q22, e4, co, so, k0, k1;
 };
 
 struct RefPoint {
@@ -235,6 +237,54 @@ __device__ __forceinline__ ObsRow obstacle_row(const ObsL& ob, float px, float p
   return R;
 }
 
+// Super-ellipse row (e = 4), eqs. (16)-(17): h = k0 y0^4 + k1 y1^4 - 1 in the
+// obstacle frame (y = R d).  Per axis the expansion hhat = h + Ts hd +
+// Ts^2/2 hdd and its partials in y, y_dot and y_ddot (third derivatives of h
+// included) are formed, then chained to the state through y_dot = v e1' - vo'
+// and y_ddot = a e1' + v^2 kd e2' (primes: obstacle frame).
+__device__ __forceinline__ ObsRow obstacle_row_e4(const ObsL& ob, float px, float py, float v, float a, float c1,
+                                                  float s1, float vkd, float sec2, float t, float Ts, float Ts2,
+                                                  float inv_l1) {
+  const float co = ob.co, so = ob.so;
+  const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
+  const float y0 = co * dx + so * dy, y1 = -so * dx + co * dy;
+  const float e10 = co * c1 + so * s1, e11 = -so * c1 + co * s1;   // R e1; R e2 = (-e11, e10)
+  const float vo0 = co * ob.vx + so * ob.vy, vo1 = -so * ob.vx + co * ob.vy;
+  const float v2kd = v * vkd;
+  const float yd0 = v * e10 - vo0, yd1 = v * e11 - vo1;
+  const float ydd0 = a * e10 - v2kd * e11, ydd1 = a * e11 + v2kd * e10;
+  float hh[2], P[2], V[2], A[2];
+  const float k[2] = {ob.k0, ob.k1}, y[2] = {y0, y1}, yd[2] = {yd0, yd1}, ydd[2] = {ydd0, ydd1};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float y2 = y[i] * y[i], y3 = y2 * y[i];
+    const float f1 = 4.0f * k[i] * y3, f2 = 12.0f * k[i] * y2, f3 = 24.0f * k[i] * y[i];
+    const float hd = f1 * yd[i], hdd = f2 * yd[i] * yd[i] + f1 * ydd[i];
+    hh[i] = k[i] * y2 * y2 + Ts * hd + 0.5f * Ts2 * hdd;
+    P[i] = f1 + Ts * f2 * yd[i] + 0.5f * Ts2 * (f3 * yd[i] * yd[i] + f2 * ydd[i]);   // d hhat / d y
+    V[i] = Ts * f1 + Ts2 * f2 * yd[i];                                             // d hhat / d y_dot
+    A[i] = 0.5f * Ts2 * f1;                                                        // d hhat / d y_ddot
+  }
+  const float Ae1 = A[0] * e10 + A[1] * e11, Ae2 = -A[0] * e11 + A[1] * e10;
+  const float Ve1 = V[0] * e10 + V[1] * e11, Ve2 = -V[0] * e11 + V[1] * e10;
+  const float Pe1 = P[0] * e10 + P[1] * e11, Pvo = P[0] * vo0 + P[1] * vo1;
+  const float h_v = Ve1 + 2.0f * vkd * Ae2;
+  const float h_th = v * Ve2 + a * Ae2 - v2kd * Ae1;
+  ObsRow R;
+  R.hhat = hh[0] + hh[1] - 1.0f;
+  R.Lf = Ts * (v * Pe1 + h_v * a + h_th * vkd - Pvo);
+  R.g0 = Ts * Ae1;                                  // Ts d hhat/da
+  R.g1 = Ts * v * v * sec2 * inv_l1 * Ae2;          // Ts d hhat/d delta
+  return R;
+}
+
+__device__ __forceinline__ ObsRow obstacle_row_any(const ObsL& ob, float px, float py, float v, float a, float c1,
+                                                   float s1, float vkd, float sec2, float t, float Ts, float Ts2,
+                                                   float inv_l1) {
+  if (ob.e4 != 0.0f) return obstacle_row_e4(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+  return obstacle_row(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+}
+
 // value held by lane Q of each G-lane group, broadcast to the group (DPP quad
 // permute; G = 2 or 4 divides a quad, G = 8 groups hold two quads that each
 // carry the value)
@@ -311,7 +361,14 @@ __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, in
   for (int o = 0; o < n_obs; ++o) {
     const ObsL ob = sobs[o];
     const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
-    const float h = dx * (ob.q11 * dx + ob.q12 * dy) + dy * (ob.q12 * dx + ob.q22 * dy) - 1.0f;
+    float h;
+    if (ob.e4 != 0.0f) {
+      const float y0 = ob.co * dx + ob.so * dy, y1 = -ob.so * dx + ob.co * dy;
+      const float z0 = y0 * y0, z1 = y1 * y1;
+      h = ob.k0 * z0 * z0 + ob.k1 * z1 * z1 - 1.0f;
+    } else {
+      h = dx * (ob.q11 * dx + ob.q12 * dy) + dy * (ob.q12 * dx + ob.q22 * dy) - 1.0f;
+    }
     pen += (h < 0.0f) ? h * h : 0.0f;
   }
   return pen;
@@ -549,14 +606,14 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           const int o = g + G * j;
           if constexpr (G == 1) {
             if (o < n_obs) {
-              const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+              const ObsRow R = obstacle_row_any(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
               O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
               acc_row(A, O[j]);
             }
           } else if (G * j < n_obs) {
             // lanes past the last obstacle compute a row from an in-range LDS
             // slot and contribute zeros, without a divergent branch
-            const ObsRow R = obstacle_row(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+            const ObsRow R = obstacle_row_any(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
             RowTerms Rt = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
             if (!(o < n_obs)) Rt.c = Rt.g0 = Rt.g1 = Rt.rr = Rt.Lf = Rt.ih = 0.0f;
             O[j] = Rt;
@@ -1163,7 +1220,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
       L.q11 = co * co * iax + so * so * iay;
       L.q12 = co * so * (iax - iay);
       L.q22 = so * so * iax + co * co * iay;
-      L.pad = 0.0f;
+      L.e4 = (o.e == 4.0f) ? 1.0f : 0.0f;
+      L.co = co;
+      L.so = so;
+      L.k0 = iax * iax;
+      L.k1 = iay * iay;
       s_obs[threadIdx.x] = L;
     }
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {

@@ -343,7 +343,7 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (!std::isfinite(p->t0)) return fail(BRMPPI_EINVAL, "t0 must be finite");
   for (uint32_t i = 0; i < p->n_obs; ++i) {
     const brmppi_obstacle& o = p->obs[i];
-    if (o.e != 2.0f) return fail(BRMPPI_EINVAL, "only e == 2 obstacles are implemented");
+    if (o.e != 2.0f && o.e != 4.0f) return fail(BRMPPI_EINVAL, "obstacle exponent e must be 2 or 4");
     const float v[8] = {o.cx, o.cy, o.mx, o.my, o.heading, o.e, o.vx, o.vy};
     for (float x : v)
       if (!std::isfinite(x)) return fail(BRMPPI_EINVAL, "non-finite obstacle field");

@@ -162,13 +162,20 @@ def test_closed_loop_matches_plain_and_oracle_plant(ctx):
         assert np.allclose(x_cl[k + 1], want, rtol=1e-14, atol=1e-14), k
 
 
-@pytest.mark.parametrize("n_obs,flags", [(7, 0), (2, 0), (13, W.FLAG_HITCH_OFF), (29, 0), (5, W.FLAG_GUIDANCE_OFF),
-                                         (7, W.FLAG_COLLISION_PENALTY),
-                                         (4, W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY)])
-def test_launch_shapes_bitwise_identical(ctx, n_obs, flags):
+@pytest.mark.parametrize("n_obs,flags,e4", [(7, 0, False), (2, 0, False), (13, W.FLAG_HITCH_OFF, False),
+                                            (29, 0, False), (5, W.FLAG_GUIDANCE_OFF, False),
+                                            (7, W.FLAG_COLLISION_PENALTY, False),
+                                            (4, W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY, False),
+                                            (9, 0, True), (6, W.FLAG_COLLISION_PENALTY, True)])
+def test_launch_shapes_bitwise_identical(ctx, n_obs, flags, e4):
     """every (block size, lanes per sample, noise source) gives the same bits:
-    costs, applied sequences and the update"""
+    costs, applied sequences and the update (e4: every other obstacle a
+    super-ellipse, so lanes of a group take different row code)"""
     p = W.random_small(80 + n_obs, S=2999, T=12, n_obs=n_obs).copy(flags=flags)
+    if e4:
+        obs = p.obstacles.copy()
+        obs[1::2, 5] = 4.0
+        p = p.copy(obstacles=obs)
     ctx.set_path(406, p.path, p.ds)
     B.brmppi_set_launch(ctx.h, 64, 0)
     ref = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=406), want_J=True, want_useq=True)
@@ -223,7 +230,7 @@ def test_invalid_arguments_leave_state(ctx):
         B.brmppi_solve(ctx.h, B.ProblemBuffers(bad, controller=407))
     assert e.value.code == B.EINVAL
     obs = p.obstacles.copy()
-    obs[0, 5] = 4.0                          # e = 4 is not implemented
+    obs[0, 5] = 3.0                          # only e = 2 and e = 4 are implemented
     with pytest.raises(B.BrmppiError) as e:
         B.brmppi_solve(ctx.h, B.ProblemBuffers(p.copy(obstacles=obs), controller=407))
     assert e.value.code == B.EINVAL

@@ -128,6 +128,23 @@ def test_collision_penalty_baseline(ctx, flags):
     assert np.count_nonzero(o["J"] > plain["J"]) > 0        # the penalty was active
 
 
+@pytest.mark.parametrize("seed,n_obs,which", [(50, 6, "all"), (51, 9, "odd"), (52, 32, "odd"), (53, 3, "all")])
+def test_super_ellipse_obstacles(ctx, seed, n_obs, which):
+    """e = 4 obstacles (the paper's parked vehicles), alone or mixed with
+    e = 2 ones, against the oracle"""
+    from oracle import oracle as O
+    prob = W.random_small(seed, S=900, T=15, n_obs=n_obs)
+    obs = prob.obstacles.copy()
+    if which == "all":
+        obs[:, 5] = 4.0
+    else:
+        obs[1::2, 5] = 4.0
+    prob = prob.copy(obstacles=obs)
+    g = run_gpu(ctx, prob, controller=24)
+    o = O.solve(prob, nthreads=NTHREADS)
+    compare(prob, g, o, f"e4 seed={seed} n_obs={n_obs} {which}")
+
+
 @pytest.mark.parametrize("S,T,n_obs", [(1, 1, 0), (1, 5, 3), (63, 2, 32), (257, 1, 1), (1025, 3, 16)])
 def test_edge_shapes(ctx, S, T, n_obs):
     from oracle import oracle as O
