@@ -33,7 +33,7 @@ struct alignas(16) SolveDesc {
   uint32_t n_path, instance, seed_lo, seed_hi;
   uint32_t S_pad, n_wchunk, n_rgroup, n_ritems;
   uint32_t x0_resident, n_normals, fused, ustar_global;   // n_normals: 5 + n_obs (guided) or 3
-  uint32_t n_units, pad1, pad2, pad3;
+  uint32_t n_units, any_e4, pad2, pad3;   // any_e4: some obstacle has e = 4
   const float4* path;           // controller path (absolute coordinates)
   const float* u_nom_in;        // 3T nominal sequence read by the rollout
   float* u_nom_out;             // 3T warm-start slot of the controller (shift target)

@@ -278,10 +278,13 @@ __device__ __forceinline__ ObsRow obstacle_row_e4(const ObsL& ob, float px, floa
   return R;
 }
 
+// E4: the instance has super-ellipse obstacles (decided once per tile, so that
+// ellipse-only instances run a step loop without the e = 4 code)
+template <bool E4>
 __device__ __forceinline__ ObsRow obstacle_row_any(const ObsL& ob, float px, float py, float v, float a, float c1,
                                                    float s1, float vkd, float sec2, float t, float Ts, float Ts2,
                                                    float inv_l1) {
-  if (ob.e4 != 0.0f) return obstacle_row_e4(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+  if (E4 && ob.e4 != 0.0f) return obstacle_row_e4(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
   return obstacle_row(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
 }
 
@@ -355,6 +358,7 @@ __device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t t
 // form is not given): sum_o max(0, -h_o)^2 with h_o = d'Q d - 1 the e = 2
 // obstacle function of eq. (16) at the current position and time, in
 // obstacle order (every lane of a group sums all obstacles).
+template <bool E4>
 __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, int n_obs, float px, float py,
                                                float t) {
   float pen = 0.0f;
@@ -362,7 +366,7 @@ __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, in
     const ObsL ob = sobs[o];
     const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
     float h;
-    if (ob.e4 != 0.0f) {
+    if (E4 && ob.e4 != 0.0f) {
       const float y0 = ob.co * dx + ob.so * dy, y1 = -ob.so * dx + ob.co * dy;
       const float z0 = y0 * y0, z1 = y1 * y1;
       h = ob.k0 * z0 * z0 + ob.k1 * z1 * z1 - 1.0f;
@@ -434,9 +438,9 @@ __device__ __forceinline__ float tracking_cost_sc(const brmppi_params& P, const 
 // Rows: every lane computes the hitch row g mod 2 (G = 1: both), obstacle o is
 // computed by lane o mod G in its slot o / G.  After the projection every lane
 // holds the same inputs, state and cost.
-template <int NOB, bool GUIDED, int G, bool PRE>
 // s_u / s_J (fused epilogue): the tile's applied inputs [3T][lds_stride] and
 // costs in LDS, at column t_local.
+template <int NOB, bool GUIDED, int G, bool PRE, bool E4>
 __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
                                                int w0, int nw, int k0, float phi0, float* s_u, uint32_t lds_stride,
@@ -606,14 +610,14 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           const int o = g + G * j;
           if constexpr (G == 1) {
             if (o < n_obs) {
-              const ObsRow R = obstacle_row_any(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+              const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
               O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
               acc_row(A, O[j]);
             }
           } else if (G * j < n_obs) {
             // lanes past the last obstacle compute a row from an in-range LDS
             // slot and contribute zeros, without a divergent branch
-            const ObsRow R = obstacle_row_any(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+            const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
             RowTerms Rt = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
             if (!(o < n_obs)) Rt.c = Rt.g0 = Rt.g1 = Rt.rr = Rt.Lf = Rt.ih = 0.0f;
             O[j] = Rt;
@@ -646,7 +650,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float prog = P.nu_bar - unu;
     float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
                P.R_w * uw * uw + P.mu * prog * prog;
-    if (penalty) rc += P.w_col * collision_pen(sobs, n_obs, px, py, d.t0 + (float)tau * Ts);
+    if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)tau * Ts);
     J += (double)rc;
 
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
@@ -682,7 +686,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   }
   const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);
-  if (penalty) rN += P.w_col * collision_pen(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
+  if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
   J += (double)rN;
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
@@ -1256,8 +1260,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
     const int g = (int)(threadIdx.x % G);
     const bool valid = s_raw < d.S;
     const uint32_t s = valid ? s_raw : d.S - 1;
-    rollout_sample<NOB, GUIDED, G, PRE>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
-                                        lds_stride, t_local, s_J);
+    if (d.any_e4)
+      rollout_sample<NOB, GUIDED, G, PRE, true>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
+                                                lds_stride, t_local, s_J);
+    else
+      rollout_sample<NOB, GUIDED, G, PRE, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
+                                                 lds_stride, t_local, s_J);
     __syncthreads();
     if (fused) tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);
   }

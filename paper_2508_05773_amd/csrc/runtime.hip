@@ -408,7 +408,10 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.plant_x = c.plant;
   d.n_normals = normals_per_step(p);
   d.noise = L.n_normals ? reinterpret_cast<float*>(base + L.off_noise) : nullptr;
-  for (uint32_t i = 0; i < p.n_obs; ++i) d.obs[i] = p.obs[i];
+  for (uint32_t i = 0; i < p.n_obs; ++i) {
+    d.obs[i] = p.obs[i];
+    if (p.obs[i].e == 4.0f) d.any_e4 = 1u;
+  }
 }
 
 // launch shape of a plain (single-instance) rollout
