@@ -1428,7 +1428,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
   std::lock_guard<std::mutex> lk(ctx->mu);
   // synthetic problems: straight path, obstacles alternating on both sides
-  const uint32_t T = 16;
+  const uint32_t T = 48;           // long enough that the step loop, not launch and reduction, dominates
   const uint32_t n_path = 400;
   const uint32_t S_rep[4] = {2048, 8192, 32768, 65536};   // one per S class
   std::vector<float> path(4 * n_path);
