@@ -34,6 +34,7 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (packed), AMD spec
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_05773_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_c2_traffic.json")
+LEGS = ("latency", "batched", "served", "paper", "large")
 
 
 # ---------------------------------------------------------------------------
@@ -100,6 +101,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
     ap.add_argument("--tune-file", default=None,
                     help="launch-shape table: used as is when it exists, else written by the autotune")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="extra legs to run after the timed loop (comma list of %s)" % ", ".join(LEGS))
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -193,9 +196,21 @@ def main():
         },
     }
 
-    if not args.no_extras:
-        out.update(extras(args, B, W, ctx, prob))
+    legs = set() if args.no_extras else {x for x in args.legs.split(",") if x}
+    bad = legs - set(LEGS)
+    if bad:
+        ap.error(f"unknown legs {sorted(bad)}")
+    if "large" in legs:
+        out["large"] = large_leg(B, W, ctx, tune_file if not args.no_autotune else None)
     ctx.close()
+    if legs - {"large"}:
+        # the other legs run on a context without kernel timing: with timing on,
+        # a batch is launched directly instead of replayed from its HIP graph,
+        # and every timed launch records two events
+        ctx2 = B.Context(arena_bytes=3 << 30, n_streams=2, max_controllers=600, profile=False,
+                         autotune_cache=tune_file)
+        out.update(extras(args, B, W, ctx2, prob, legs))
+        ctx2.close()
 
     if not args.no_cpu:
         note("cpu baseline (oracle)")
@@ -203,12 +218,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(args, B, W, ctx, prob):
-    import torch
+def extras(args, B, W, ctx, prob, legs):
+    res = {}
+    if "latency" in legs:
+        note("plain-solve latency")
+        res.update(latency_leg(args, B, ctx, prob))
+    if "batched" in legs:
+        note("batched vs plain")
+        res["batched"] = batched_leg(B, W, ctx)
+    if "served" in legs:
+        note("served")
+        # ---- served: continuous batching of 256 controllers vs sequential plain ----
+        res["served"] = served_leg(args, B, W, ctx)
+    if "paper" in legs:
+        note("paper shape")
+        res["paper_shape"] = paper_leg(B, W, ctx)
+    return res
 
+
+def latency_leg(args, B, ctx, prob):
     h = ctx.h
     res = {}
-    note("closed loop done; plain-solve latency")
     # ---- plain blocking solve latency (host in, host out) ----
     ctx.set_path(1, prob.path, prob.ds)
     lat = []
@@ -221,8 +251,13 @@ def extras(args, B, W, ctx, prob):
     res["p99_ms"] = pct(lat, 99)
     res["plain_solves_per_s"] = 1e3 / float(np.mean(lat))
     res["pcie_inclusive_sample_steps_per_s"] = prob.S * prob.T * res["plain_solves_per_s"]
+    return res
 
-    note("batched vs plain")
+
+def batched_leg(B, W, ctx):
+    import torch
+
+    h = ctx.h
     # ---- batched (one persistent launch in a HIP graph) vs plain per-instance ----
     insts = W.config3()
     for i, p in enumerate(insts):
@@ -245,18 +280,17 @@ def extras(args, B, W, ctx, prob):
         B.brmppi_solve_batch(h, pbs)
     t_batch = (time.perf_counter() - t0) / reps_b
     ss = sum(p.S * p.T for p in insts)
-    res["batched"] = {
+    return {
         "workload": "64 uneven instances: S in {1024..16384}, T in [20, 80], 0-16 obstacles",
         "instances": len(insts), "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
         "plain_solves_per_s": len(insts) / t_plain, "batched_solves_per_s": len(insts) / t_batch,
         "speedup": t_plain / t_batch, "batched_sample_steps_per_s": ss / t_batch,
+        "sample_steps": ss, "reduce_read_bytes": sum(12 * p.S * p.T + 4 * p.S for p in insts),
     }
 
-    note("served")
-    # ---- served: continuous batching of 256 controllers vs sequential plain ----
-    res["served"] = served_leg(args, B, W, ctx)
 
-    note("paper shape")
+def paper_leg(B, W, ctx):
+    h = ctx.h
     # ---- the paper's own problem shape: H = 120, 5000 rollouts, 8 obstacles ----
     # with the two MPPI baselines of the paper's comparison (plain MPPI and MPPI
     # with a collision penalty) timed the same way
@@ -272,11 +306,47 @@ def extras(args, B, W, ctx, prob):
             if k >= 5:
                 lat.append(st["latency_us"] * 1e-3)
         ps[name] = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "paper_ms": paper_ms}
-    res["paper_shape"] = {"S": 5000, "T": 120, "n_obs": 8, **ps["br_mppi"], "paper_hw": "unnamed single GPU, JAX",
-                          "baselines": {"mppi": ps["mppi"], "mppi_col": ps["mppi_col"]},
-                          "note": "paper_ms: forward-parking times of the paper's comparison (its table of "
-                                  "MPPI, MPPI + collision cost, BR-MPPI)"}
-    return res
+    return {"S": 5000, "T": 120, "n_obs": 8, **ps["br_mppi"], "paper_hw": "unnamed single GPU, JAX",
+            "baselines": {"mppi": ps["mppi"], "mppi_col": ps["mppi_col"]},
+            "note": "paper_ms: forward-parking times of the paper's comparison (its table of "
+                    "MPPI, MPPI + collision cost, BR-MPPI)"}
+
+
+def large_leg(B, W, ctx, tune_file):
+    import torch
+
+    h = ctx.h
+    note("large solve")
+    # ---- one large update (S = 65536, T = 100, 32 obstacles): enough waves to
+    # fill every SIMD, so the rollout's fraction of peak is not occupancy-bound ----
+    big = W.config5()
+    ctx.set_path(3, big.path, big.ds)
+    for k in range(2):
+        B.brmppi_solve(h, B.ProblemBuffers(big, controller=3, with_nominal=(k == 0), seed=k))
+    torch.cuda.synchronize()
+    B.brmppi_profile_reset(h)
+    lat = []
+    for k in range(10):
+        _, st, _ = B.brmppi_solve(h, B.ProblemBuffers(big, controller=3, with_nominal=False, seed=10 + k))
+        lat.append(st["latency_us"] * 1e-3)
+    prof = B.brmppi_profile_read(h)
+    roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
+    noise_in_kernel = prof["noise"]["count"] == 0
+    fl = rollout_flops(big.S, big.T, big.n_obs, noise_in_kernel=noise_in_kernel)
+    ach = fl / (roll_ms * 1e-3) / 1e12
+    shape = None
+    try:
+        shape = json.load(open(tune_file)).get("plain_32_3") if tune_file else None
+    except (OSError, ValueError):
+        pass
+    return {"workload": "S=65536, T=100, 32 ellipses, three-piece spline path with cusps",
+            "launch_shape": {"block_variant": shape},
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "sample_steps_per_s": big.S * big.T / (pct(lat, 50) * 1e-3),
+            "rollout_ms": roll_ms, "noise_ms": prof["noise"]["ms"] / max(len(lat), 1),
+            "rollout_tflops": ach, "rollout_frac": ach / PEAK_FP32_TFLOPS,
+            "rollout_frac_nonpacked": ach / PEAK_FP32_NONPACKED_TFLOPS,
+            "flops_per_launch": fl}
 
 
 def served_leg(args, B, W, ctx):

@@ -67,7 +67,7 @@ extern "C" {
                                      to [j_lo, j_hi], [w_lo, w_hi]) with eq. (6) in FP64 */
 #define BRMPPI_COLLISION_PENALTY 16u /* the paper's second baseline (Sec. V), whose form it
                                      does not give: w_col * sum_o max(0, -h_o(x, t))^2,
-                                     h_o the e = 2 obstacle function of eq. (16) at the
+                                     h_o the obstacle function of eq. (16) at the
                                      current state, added to every stage cost and to the
                                      terminal cost; usually with BRMPPI_GUIDANCE_OFF */
 #define BRMPPI_HITCH_QP 32u       /* hitch-angle stabiliser (Sec. IV-D, eq. (19)) before the

@@ -148,11 +148,11 @@ __device__ __forceinline__ float tracking_cost(const brmppi_params& P, const Ref
 // ---------------------------------------------------------------------------
 // Rollout
 // ---------------------------------------------------------------------------
-// Launch shapes: G lanes share one sample (G = 1, 2, 4).  Every lane of a group
+// Launch shapes: G lanes share one sample (G = 1, 2, 4, 8).  Every lane of a group
 // carries the full state; obstacle o's barrier row is computed by group lane
-// o % G, and its projection terms are broadcast to the group with DPP quad
-// permutes, so that every lane accumulates all rows in the same canonical
-// order (hitch+, hitch-, obstacles) as a one-lane sample does.  With PRE the
+// o % G, and the rows' projection terms are summed over the group by DPP
+// butterflies in a canonical tree of eight virtual lanes (below), so that
+// every lane ends with the same sums, bit for bit, as a one-lane sample.  With PRE the
 // normals come from the noise buffer filled by k_noise (same Philox and
 // Box-Muller code) instead of being drawn in the rollout.  Results are
 // therefore bitwise identical for every (G, PRE) and block size.
@@ -355,9 +355,9 @@ __device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t t
 }
 
 // Collision-penalty baseline (the paper's second MPPI baseline, Sec. V; its
-// form is not given): sum_o max(0, -h_o)^2 with h_o = d'Q d - 1 the e = 2
-// obstacle function of eq. (16) at the current position and time, in
-// obstacle order (every lane of a group sums all obstacles).
+// form is not given): sum_o max(0, -h_o)^2 with h_o the obstacle function of
+// eq. (16) (e = 2 or 4) at the current position and time, in obstacle order
+// (every lane of a group sums all obstacles).
 template <bool E4>
 __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, int n_obs, float px, float py,
                                                float t) {
@@ -926,11 +926,11 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float* s_red) {
   b = rb;
 }
 
-// Merge of the chunk partials by the last block of an instance: global min
-// m = min_c m_c, chunk scale exp(-(m_c - m)/lambda), Z and sum of squared
-// weights, then U = sum_c scale_c rpart[c] / Z per row (eq. (5)).  Every load
-// is issued by a different thread or unrolled, so the merge costs a few memory
-// latencies, not one per chunk.
+// Merge of the group partials (a group = 1024 samples) by the last block of an
+// instance: global min m = min_c m_c, group scale exp(-(m_c - m)/lambda), Z
+// and sum of squared weights, then U = sum_c scale_c rpart[c] / Z per row
+// (eq. (5)).  Every load is issued by a different thread or unrolled, so the
+// merge costs a few memory latencies, not one per group.
 __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_red, double* s_plant) {
   const uint32_t nW = d.n_wchunk;
   const uint32_t R = 3 * d.T;
