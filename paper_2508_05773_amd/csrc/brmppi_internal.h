@@ -15,7 +15,8 @@ constexpr int kUnit = 32;                    // samples per unit
 constexpr int kGroupUnits = 32;              // units per group
 constexpr int kWChunk = kUnit * kGroupUnits; // samples per group
 constexpr int kWThreads = 256;    // threads of the reduce kernel
-constexpr int kRowsPerBlock = 8;  // (step, input) rows per reduce work item: two per wave
+constexpr int kRowsPerPass = 8;   // (step, input) rows one pass of the reduce block covers: two per wave
+constexpr int kMaxRowsPerItem = 64;  // rows of one reduce work item (a multiple of kRowsPerPass)
 constexpr size_t kFusedLdsMax = 64 * 1024;   // dynamic LDS bound of the fused rollout
 constexpr uint32_t kCtrStride = 32;          // completion counters one 128-B line apart
 constexpr int kPathWin = 1024;    // waypoints staged in LDS per tile
@@ -25,7 +26,7 @@ constexpr int kNoisePrefetch = 2;   // steps of normals loaded ahead of their us
 
 // Per-update descriptor read by every kernel (device memory).
 struct alignas(16) SolveDesc {
-  brmppi_params prm;            // 31 floats
+  brmppi_params prm;            // 35 floats
   float inv_lambda;
   float x0[8];                  // px, py, v, a, th1, th2, delta, psi
   float t0, lambda, ds, inv_ds;
@@ -33,7 +34,8 @@ struct alignas(16) SolveDesc {
   uint32_t n_path, instance, seed_lo, seed_hi;
   uint32_t S_pad, n_wchunk, n_rgroup, n_ritems;
   uint32_t x0_resident, n_normals, fused, ustar_global;   // n_normals: 5 + n_obs (guided) or 3
-  uint32_t n_units, any_e4, pad2, pad3;   // any_e4: some obstacle has e = 4
+  uint32_t n_units, any_e4, rows_item, pad3;   // any_e4: some obstacle has e = 4; rows_item: rows
+                                               // of one reduce work item
   const float4* path;           // controller path (absolute coordinates)
   const float* u_nom_in;        // 3T nominal sequence read by the rollout
   float* u_nom_out;             // 3T warm-start slot of the controller (shift target)
@@ -49,7 +51,7 @@ struct alignas(16) SolveDesc {
   float* u_new;                 // [3T] result
   float* stats;                 // [4] J_min, Z, ess, status
   double* plant_x;              // [8] resident plant state
-  float* noise;                 // [T][n_normals][S_pad] precomputed normals (variants 1-3)
+  float* noise;                 // [T][n_normals][S_pad] precomputed normals (variants 1-4)
   brmppi_obstacle obs[BRMPPI_MAX_OBS];
 };
 
@@ -64,8 +66,8 @@ struct alignas(16) BatchCounters {
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return hipError_t.
 // Rollout variant: 0 = one lane per sample with in-kernel noise, 1 = one lane
-// with precomputed noise, 2 / 3 = two / four lanes per sample with
-// precomputed noise (k_noise must run first).  All variants give bitwise
+// with precomputed noise, 2 / 3 / 4 = two / four / eight lanes per sample
+// with precomputed noise (k_noise must run first).  All variants give bitwise
 // identical results.
 constexpr int kMaxVariant = 4;   // 0: G1 fused noise, 1: G1, 2: G2, 3: G4, 4: G8 (precomputed noise)
 int variant_lanes(int variant);

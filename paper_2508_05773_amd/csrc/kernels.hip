@@ -1096,6 +1096,19 @@ __device__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint
 // Fused reduction of one tile (its samples' costs and applied inputs are in
 // LDS): unit weights, unit partials to HBM; the last tile of each group merges
 // the group, the last group the instance (U_new, shift, plant step).
+// Waves per SIMD the register allocation must leave room for.  Up to 16
+// obstacle slots every launch shape fits two waves (the one-lane forms with a
+// few spilled values, which still pays: at one wave per SIMD nothing hides the
+// step's latency); with 32 slots the one-lane forms would spill hundreds of
+// values, so they keep the whole register file.
+template <int NOB>
+constexpr int rollout_waves_per_simd() {
+  return NOB <= 16 ? 2 : 1;
+}
+
+// W: the calling kernels' waves per SIMD.  Each class of callers gets its own
+// copy, so that the copy is compiled within the same register budget.
+template <int W>
 __device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile, float* s_u, uint32_t lds_stride,
                               const float* s_J, float* s_gam, float* s_mu, float* s_sig, float4* s_up,
                               float* s_red, double* s_trig, uint32_t* s_flag) {
@@ -1155,7 +1168,8 @@ __device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile
 }
 
 template <int NOB, bool GUIDED, int G, bool PRE>
-__global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restrict__ descs,
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_simd<NOB>(), 8)))
+void k_rollout(const SolveDesc* __restrict__ descs,
                                                        const Tile* __restrict__ tiles, uint32_t n_tiles,
                                                        BatchCounters* __restrict__ ctr) {
   __shared__ float4 s_path[kPathWin];
@@ -1267,7 +1281,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
       rollout_sample<NOB, GUIDED, G, PRE, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
                                                  lds_stride, t_local, s_J);
     __syncthreads();
-    if (fused) tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);
+    if (fused)
+      tile_epilogue<rollout_waves_per_simd<NOB>()>(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig,
+                                                   s_up, s_red, s_trig, &s_flag);
   }
   if (ctr && threadIdx.x == 0) {
     fence_release();
@@ -1280,25 +1296,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_rollout(const SolveDesc* __restri
 }
 
 constexpr uint32_t kMaxWChunks = BRMPPI_MAX_S / kWChunk;
-static_assert(kRowsPerBlock == 2 * (kWThreads / 64), "two rows per wave");
+static_assert(kRowsPerPass == 2 * (kWThreads / 64), "two rows per wave and pass");
+static_assert(kMaxRowsPerItem % kRowsPerPass == 0 && kMaxRowsPerItem <= kWThreads, "whole passes");
 static_assert(kWChunk == 4 * kWThreads, "four samples per thread");
 static_assert(kUnit == 32 && kGroupUnits == 32, "a unit is half a wave; a group's units fit one wave");
 
 // Reduction from the applied inputs in HBM (batched launches and tiles that
 // are not whole units), with the same canonical structure as the fused
-// epilogue.  Work item = (group of 1024 samples, 8 rows): the group's unit
-// weights are recomputed from its 4 KB of costs (same code: same values), the
-// first row block also stores the group's (m_g, Z_g, Z2_g).  Half-wave h of
-// wave w takes row 8 rg + 2 w + h, lane u of it unit u's 32 samples; the unit
-// sums are merged in unit order by one thread per row.  The last block of the
-// instance merges the groups.
+// epilogue.  Work item = (group of 1024 samples, d.rows_item rows): the
+// group's unit weights are recomputed from its 4 KB of costs (same code: same
+// values), the first row block also stores the group's (m_g, Z_g, Z2_g).  The
+// item's rows are taken in passes of 8: half-wave h of wave w takes row
+// 2 w + h of the pass, lane u of it unit u's 32 samples, and the loads of the
+// next pass are in flight while the current one is summed.  The unit sums are
+// merged in unit order by one thread per row, and the item is published once.
+// The last block of the instance merges the groups.
 __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restrict__ descs,
                                                      const Item* __restrict__ items, uint32_t n_items,
                                                      BatchCounters* __restrict__ ctr) {
   __shared__ float4 s_gam4[kWChunk / 4];
   __shared__ float s_mu[kGroupUnits], s_sig[kGroupUnits];
   __shared__ float4 s_up[kGroupUnits];
-  __shared__ float s_R[kRowsPerBlock][kGroupUnits];
+  __shared__ float s_R[kMaxRowsPerItem][kGroupUnits + 1];   // +1: row-wise reads hit distinct banks
   __shared__ float s_red[2 * (kWThreads / 64)];
   __shared__ float s_scale[kMaxWChunks];
   __shared__ double s_trig[kPlantLds];
@@ -1323,18 +1342,23 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     const uint32_t S = d.S;
     const uint32_t gu0 = grp * kGroupUnits;
     const uint32_t nu_g = min((uint32_t)kGroupUnits, d.n_units - gu0);
+    const uint32_t r0 = rg * d.rows_item;
+    const uint32_t nrow = min(d.rows_item, R - r0);
+    const uint32_t n_pass = (nrow + kRowsPerPass - 1) / kRowsPerPass;
 
-    // this lane's row and unit; its 32 applied inputs are loaded first so that
-    // their latency overlaps the weights
+    // this lane's row in each pass and its unit; the first pass's applied
+    // inputs are loaded first so that their latency overlaps the weights
     const uint32_t h = (uint32_t)lane >> 5, u = (uint32_t)lane & 31u;
     const uint32_t rl = 2 * wid + h;
-    const uint32_t r = rg * kRowsPerBlock + rl;
-    const bool rv = (r < R) && (u < nu_g);
+    const float* __restrict__ colp = d.u_star + base + kUnit * u;
     float4 uv[kUnit / 4];
-    const float* __restrict__ rowp = d.u_star + (size_t)(rv ? r : 0) * d.S_pad + base + kUnit * u;
+    {
+      const bool rv = (rl < nrow) && (u < nu_g);
+      const float* __restrict__ rowp = colp + (size_t)(rv ? r0 + rl : 0) * d.S_pad;
 #pragma unroll
-    for (int k = 0; k < kUnit / 4; ++k)
-      uv[k] = rv ? *reinterpret_cast<const float4*>(rowp + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int k = 0; k < kUnit / 4; ++k)
+        uv[k] = rv ? *reinterpret_cast<const float4*>(rowp + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 
     // costs (thread t: samples 4t .. 4t + 3 of the group; unit t / 8)
     const uint32_t s4 = base + 4 * t;
@@ -1374,18 +1398,31 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       }
       if (lane == 0) s_red[0] = mg;
     }
-    // unit row sums, in sample order
-    if (rv) {
-      const float* gam = s_gam + kUnit * u;
-      float acc = 0.0f;
+    // unit row sums, in sample order, pass by pass
+    const float* gam = s_gam + kUnit * u;
+    for (uint32_t p = 0; p < n_pass; ++p) {
+      const uint32_t rp = p * kRowsPerPass + rl;          // row within the item
+      const bool rv = (rp < nrow) && (u < nu_g);
+      const uint32_t rn = rp + kRowsPerPass;              // next pass
+      const bool nv = (rn < nrow) && (u < nu_g);
+      float4 un[kUnit / 4];
+      const float* __restrict__ rowq = colp + (size_t)(nv ? r0 + rn : 0) * d.S_pad;
 #pragma unroll
-      for (int k = 0; k < kUnit / 4; ++k) {
-        acc = unit_row_term(acc, gam[4 * k + 0], uv[k].x);
-        acc = unit_row_term(acc, gam[4 * k + 1], uv[k].y);
-        acc = unit_row_term(acc, gam[4 * k + 2], uv[k].z);
-        acc = unit_row_term(acc, gam[4 * k + 3], uv[k].w);
+      for (int k = 0; k < kUnit / 4; ++k)
+        un[k] = nv ? *reinterpret_cast<const float4*>(rowq + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (rv) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kUnit / 4; ++k) {
+          acc = unit_row_term(acc, gam[4 * k + 0], uv[k].x);
+          acc = unit_row_term(acc, gam[4 * k + 1], uv[k].y);
+          acc = unit_row_term(acc, gam[4 * k + 2], uv[k].z);
+          acc = unit_row_term(acc, gam[4 * k + 3], uv[k].w);
+        }
+        s_R[rp][u] = acc;
       }
-      s_R[rl][u] = acc;
+#pragma unroll
+      for (int k = 0; k < kUnit / 4; ++k) uv[k] = un[k];
     }
     __syncthreads();
     if (rg == 0 && t == 0) {
@@ -1394,13 +1431,10 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       d.wpart[grp] = make_float4(s_red[0], z, z2, 0.0f);
     }
     // group row sums, in unit order
-    if (t < kRowsPerBlock) {
-      const uint32_t rr = rg * kRowsPerBlock + t;
-      if (rr < R) {
-        float acc = 0.0f;
-        for (uint32_t v = 0; v < nu_g; ++v) acc = unit_row_term(acc, s_sig[v], s_R[t][v]);
-        d.rpart[(size_t)grp * R + rr] = acc;
-      }
+    if (t < nrow) {
+      float acc = 0.0f;
+      for (uint32_t v = 0; v < nu_g; ++v) acc = unit_row_term(acc, s_sig[v], s_R[t][v]);
+      d.rpart[(size_t)grp * R + r0 + t] = acc;
     }
     // publish: the barrier completes every wave's stores, one release by
     // thread 0 then makes them visible to the block that finishes the instance

@@ -148,6 +148,7 @@ struct ScratchLayout {
   size_t off_ustar, off_J, off_wpart, off_rpart, off_upart, off_urow, off_out, off_noise, bytes;
   uint32_t S_pad, n_wchunk, n_rgroup, n_normals;  // n_normals > 0: a noise buffer is included
   uint32_t n_units;
+  uint32_t rows_item;   // rows of one reduce work item
 };
 
 // one instance's uploaded inputs: [descriptor | reduce counter (zero) | nominal
@@ -175,13 +176,15 @@ uint32_t normals_per_step(const brmppi_problem& p) {
   return (p.flags & BRMPPI_GUIDANCE_OFF) ? 3u : 5u + p.n_obs;
 }
 
-ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0) {
+ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0,
+                             uint32_t rows_item = kRowsPerPass) {
   ScratchLayout L;
   L.n_normals = noise_normals;
   L.S_pad = (uint32_t)round_up(S, 256);
   L.n_wchunk = (S + kWChunk - 1) / kWChunk;
   L.n_units = (S + kUnit - 1) / kUnit;
-  L.n_rgroup = (3 * T + kRowsPerBlock - 1) / kRowsPerBlock;
+  L.rows_item = rows_item;
+  L.n_rgroup = (3 * T + rows_item - 1) / rows_item;
   size_t o = 0;
   L.off_ustar = o;
   o = round_up(o + (size_t)3 * T * L.S_pad * sizeof(float), 256);
@@ -201,6 +204,19 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0)
   o = round_up(o + (size_t)noise_normals * T * L.S_pad * sizeof(float), 256);
   L.bytes = o;
   return L;
+}
+
+// rows of one reduce work item for a launch over these instances: the most
+// rows (fewest barriers and publishes per byte) that still give every CU
+// several items
+uint32_t reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu) {
+  for (uint32_t r = kMaxRowsPerItem; r > kRowsPerPass; r /= 2) {
+    size_t items = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * ((3 * ps[i]->T + r - 1) / r);
+    if (items >= 6 * (size_t)n_cu) return r;
+  }
+  return kRowsPerPass;
 }
 
 // largest precomputed-noise buffer a plain solve may take
@@ -388,6 +404,7 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.n_wchunk = L.n_wchunk;
   d.n_rgroup = L.n_rgroup;
   d.n_ritems = L.n_wchunk * L.n_rgroup;
+  d.rows_item = L.rows_item;
   d.x0_resident = (p.flags & BRMPPI_X0_RESIDENT) ? 1u : 0u;
   d.path = c.path;
   d.u_nom_in = (p.u_nom && unom_dev) ? unom_dev : c.unom;
@@ -433,8 +450,9 @@ size_t fused_lds(const brmppi_problem& p, const LaunchShape& sh) {
   return b <= kFusedLdsMax ? b : 0;
 }
 
-ScratchLayout plain_layout(const brmppi_problem& p, const LaunchShape& sh) {
-  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(p) : 0u);
+ScratchLayout plain_layout(const brmppi_ctx* ctx, const brmppi_problem& p, const LaunchShape& sh) {
+  const brmppi_problem* pp = &p;
+  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(p) : 0u, reduce_rows(&pp, 1, ctx->n_cu));
 }
 
 hipEvent_t take_event(brmppi_ctx* ctx) {
@@ -533,7 +551,7 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   if (!out || !out->u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
   Controller& c = ctx->ctrl[p->controller];
   const LaunchShape sh = plain_shape(ctx, *p);
-  const ScratchLayout L = plain_layout(*p, sh);
+  const ScratchLayout L = plain_layout(ctx, *p, sh);
   // device: [scratch | input block]
   const size_t lds = fused_lds(*p, sh);
   const InputBlock IB = input_block(p->T, p->u_nom != nullptr, L.n_wchunk);
@@ -594,26 +612,71 @@ struct BatchPlan {
   // (one upload), outputs (one download), then every instance's scratch
   size_t off_descs = 0, off_tiles = 0, off_ritems = 0, off_counters = 0, header_bytes = 0;
   size_t off_outs = 0, out_floats = 0, total = 0;
-  int bucket = 0;
-  uint32_t block = 128;
+  // the instances are grouped by constraint bucket; each group's tiles are
+  // contiguous in `tiles` and run in the rollout kernel sized for that bucket
+  struct Part {
+    int bucket;
+    uint32_t block, tile0, n_tiles;
+  };
+  std::vector<Part> parts;
+  std::vector<uint32_t> inst_part;
 };
 
 void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, BatchPlan& bp) {
   bp.layouts.resize(n);
-  bp.bucket = 0;
-  for (uint32_t i = 0; i < n; ++i) bp.bucket = std::max(bp.bucket, bucket_for(ps[i]->n_obs, ps[i]->flags));
-  // a batch mixing guided and unguided instances runs the guided kernel; the
-  // unguided instances take its GUIDANCE_OFF path inside the tile loop
-  bool any_off = false, any_on = false;
-  for (uint32_t i = 0; i < n; ++i) ((ps[i]->flags & BRMPPI_GUIDANCE_OFF) ? any_off : any_on) = true;
-  if (any_on && bp.bucket == 0) bp.bucket = 2;
-  (void)any_off;
-  // a batch fills the device with samples: one lane per sample, in-kernel noise
-  bp.block = ctx->forced.block ? ctx->forced.block : ctx->batch_block[bucket_index(bp.bucket)];
-  size_t n_tiles = 0, n_r = 0;
+  // one rollout launch per constraint bucket present, heaviest first: a
+  // kernel's registers, and so how many waves share a SIMD, grow with its
+  // obstacle slots, so an instance runs in the smallest kernel that holds it.
+  // A batch fills the device with samples: one lane per sample, in-kernel noise.
+  // A bucket whose tiles would not fill two rounds of the device's resident
+  // blocks joins the next heavier bucket present: a launch lasts at least as
+  // long as its longest tile, so a thin launch costs more than the occupancy
+  // it gains.  Unguided instances (bucket 0) run in a guided kernel's
+  // GUIDANCE_OFF path when they join one.
+  bp.parts.clear();
+  bp.inst_part.assign(n, 0);
+  auto block_of = [&](int bi) { return ctx->forced.block ? ctx->forced.block : ctx->batch_block[bi]; };
+  std::vector<int> ibi(n);
+  size_t tiles_b[5] = {0, 0, 0, 0, 0};
   for (uint32_t i = 0; i < n; ++i) {
-    bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T);
-    n_tiles += (ps[i]->S + bp.block - 1) / bp.block;
+    ibi[i] = bucket_index(bucket_for(ps[i]->n_obs, ps[i]->flags));
+    tiles_b[ibi[i]] += (ps[i]->S + block_of(ibi[i]) - 1) / block_of(ibi[i]);
+  }
+  for (int bi = 0; bi < 4; ++bi) {
+    if (tiles_b[bi] == 0) continue;
+    int up = -1;
+    for (int bj = bi + 1; bj < 5 && up < 0; ++bj)
+      if (tiles_b[bj]) up = bj;
+    if (up < 0) continue;
+    const size_t resident = (size_t)ctx->n_cu * std::max(1, rollout_blocks_per_cu(kBuckets[bi], 0, block_of(bi)));
+    if (tiles_b[bi] < 2 * resident) {
+      // rescale to the receiving bucket's block size
+      size_t moved = 0;
+      for (uint32_t i = 0; i < n; ++i)
+        if (ibi[i] == bi) moved += (ps[i]->S + block_of(up) - 1) / block_of(up);
+      tiles_b[up] += moved;
+      tiles_b[bi] = 0;
+      for (uint32_t i = 0; i < n; ++i)
+        if (ibi[i] == bi) ibi[i] = up;
+    }
+  }
+  int part_of[5] = {-1, -1, -1, -1, -1};
+  for (int bi = 4; bi >= 0; --bi) {
+    for (uint32_t i = 0; i < n; ++i) {
+      if (ibi[i] != bi) continue;
+      if (part_of[bi] < 0) {
+        part_of[bi] = (int)bp.parts.size();
+        bp.parts.push_back(BatchPlan::Part{kBuckets[bi], block_of(bi), 0, 0});
+      }
+      bp.inst_part[i] = (uint32_t)part_of[bi];
+    }
+  }
+  size_t n_tiles = 0, n_r = 0;
+  const uint32_t rows_item = reduce_rows(ps, n, ctx->n_cu);
+  for (uint32_t i = 0; i < n; ++i) {
+    bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T, 0, rows_item);
+    const uint32_t blk = bp.parts[bp.inst_part[i]].block;
+    n_tiles += (ps[i]->S + blk - 1) / blk;
     n_r += (size_t)bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup;
   }
   size_t o = 0;
@@ -655,6 +718,7 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
   bp.tiles.clear();
   bp.ritems.clear();
   struct TC {
+    uint32_t part;
     double cost;
     Tile t;
   };
@@ -668,13 +732,23 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
               counter, out);
     // guidance-off instances inside a guided batch: the flag is honoured per tile
     const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + p.n_obs));
-    for (uint32_t s0 = 0; s0 < p.S; s0 += bp.block) tc.push_back({cost, Tile{i, s0}});
+    const uint32_t pi = bp.inst_part[i], blk = bp.parts[pi].block;
+    for (uint32_t s0 = 0; s0 < p.S; s0 += blk) tc.push_back({pi, cost, Tile{i, s0}});
     for (uint32_t k = 0; k < bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup; ++k) bp.ritems.push_back(Item{i, k});
   }
-  // longest tiles first (stable: instance order breaks ties)
-  std::stable_sort(tc.begin(), tc.end(), [](const TC& a, const TC& b) { return a.cost > b.cost; });
+  // tiles grouped by launch, longest first within a launch (stable: instance
+  // order breaks ties)
+  std::stable_sort(tc.begin(), tc.end(), [](const TC& a, const TC& b) {
+    return a.part != b.part ? a.part < b.part : a.cost > b.cost;
+  });
   bp.tiles.reserve(tc.size());
-  for (auto& x : tc) bp.tiles.push_back(x.t);
+  for (auto& pt : bp.parts) pt.n_tiles = 0;
+  for (size_t k = 0; k < tc.size(); ++k) {
+    BatchPlan::Part& pt = bp.parts[tc[k].part];
+    if (pt.n_tiles == 0) pt.tile0 = (uint32_t)k;
+    ++pt.n_tiles;
+    bp.tiles.push_back(tc[k].t);
+  }
 }
 
 uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_tiles) {
@@ -683,24 +757,31 @@ uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_t
   return (uint32_t)std::max<size_t>(1, std::min(g, n_tiles));
 }
 
-// persistent rollout over the tile list, then the persistent reduce (weights,
-// update, shift, plant steps) over every instance's work items
+// persistent rollouts over each bucket's tiles (one after the other: a
+// launch's work counters are zero again when it ends), then the persistent
+// reduce (weights, update, shift, plant steps) over every instance's items
 int enqueue_batch(brmppi_ctx* ctx, hipStream_t st, char* base, const BatchPlan& bp, BatchCounters* ctr,
                   bool timing) {
   const SolveDesc* descs = reinterpret_cast<const SolveDesc*>(base + bp.off_descs);
   const Tile* tiles = reinterpret_cast<const Tile*>(base + bp.off_tiles);
   const Item* ri = reinterpret_cast<const Item*>(base + bp.off_ritems);
-  const uint32_t nt = (uint32_t)bp.tiles.size(), nr = (uint32_t)bp.ritems.size();
-  const uint32_t g_roll = persistent_grid(ctx, bp.bucket, bp.block, nt);
+  const uint32_t nr = (uint32_t)bp.ritems.size();
   const uint32_t g_r = std::max<uint32_t>(1, std::min<uint32_t>(nr, (uint32_t)ctx->n_cu * 8));
-  auto L0 = [&] { return launch_rollout(bp.bucket, 0, descs, tiles, nt, ctr, g_roll, bp.block, 0, st); };
-  auto L1 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
-  int rc;
-  if (timing) {
-    if ((rc = timed(ctx, st, 0, L0))) return rc;
-    return timed(ctx, st, 1, L1);
+  for (const auto& pt : bp.parts) {
+    if (pt.n_tiles == 0) continue;
+    const uint32_t g_roll = persistent_grid(ctx, pt.bucket, pt.block, pt.n_tiles);
+    auto L0 = [&] {
+      return launch_rollout(pt.bucket, 0, descs, tiles + pt.tile0, pt.n_tiles, ctr, g_roll, pt.block, 0, st);
+    };
+    if (timing) {
+      int rc;
+      if ((rc = timed(ctx, st, 0, L0))) return rc;
+    } else {
+      HIPCHK(L0());
+    }
   }
-  HIPCHK(L0());
+  auto L1 = [&] { return launch_reduce(descs, ri, nr, ctr, g_r, st); };
+  if (timing) return timed(ctx, st, 1, L1);
   HIPCHK(L1());
   return 0;
 }
@@ -736,9 +817,14 @@ int run_batch(brmppi_ctx* ctx, hipStream_t s, char* base, const BatchPlan& bp, B
     if ((rc = enqueue_batch(ctx, s, base, bp, ctr, true))) return rc;
   } else {
     // the captured launches bake in every pointer and count: key on them
-    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(),
-                                       bp.ritems.size(), (uint64_t)bp.bucket, bp.block,
-                                       (uint64_t)(uintptr_t)s, bp.descs.size(), (uint64_t)(uintptr_t)ctr};
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)base, bp.tiles.size(), bp.ritems.size(),
+                                 (uint64_t)(uintptr_t)s, bp.descs.size(), (uint64_t)(uintptr_t)ctr};
+    for (const auto& pt : bp.parts) {
+      key.push_back((uint64_t)pt.bucket);
+      key.push_back(pt.block);
+      key.push_back(pt.tile0);
+      key.push_back(pt.n_tiles);
+    }
     if (key != ctx->graph_key || !ctx->graph_exec) {
       drop_graph(ctx);
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -834,7 +920,7 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
     return rc;
   }
   const LaunchShape sh = plain_shape(ctx, p);
-  const ScratchLayout L = plain_layout(p, sh);
+  const ScratchLayout L = plain_layout(ctx, p, sh);
   const size_t lds = fused_lds(p, sh);
   // device: [scratch | descriptors of every update | counters | nominal | logs];
   // descriptors, counters and nominal sequence travel in one upload
@@ -1488,6 +1574,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
       h.n_wchunk = L.n_wchunk;
       h.n_rgroup = L.n_rgroup;
       h.n_ritems = L.n_wchunk * L.n_rgroup;
+      h.rows_item = L.rows_item;
       h.n_units = L.n_units;
       h.n_normals = K;
       h.path = d_path;

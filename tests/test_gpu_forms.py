@@ -83,6 +83,28 @@ def test_batched_mixed_guidance_and_hitch(ctx):
         assert np.array_equal(outs[k], plain[k]), k
 
 
+def test_batched_split_by_bucket(ctx):
+    """enough 2-obstacle samples for a launch of their own beside 32-obstacle
+    and unguided instances (several rollout launches in one batch), and a thin
+    bucket that joins a heavier one: every instance equals its plain solve"""
+    probs = []
+    for k in range(12):     # 12 x 32768 samples with 2 obstacles: a launch of their own
+        probs.append(W.random_small(90 + k, S=32768, T=4, n_obs=2))
+    for k in range(3):      # a few 32-obstacle instances
+        probs.append(W.random_small(110 + k, S=3000 + 500 * k, T=5, n_obs=32))
+    probs.append(W.random_small(120, S=2500, T=6, n_obs=12))                         # thin 16-slot bucket
+    probs.append(W.random_small(121, S=1800, T=5, n_obs=3).copy(flags=W.FLAG_GUIDANCE_OFF))  # thin unguided
+    for k, p in enumerate(probs):
+        ctx.set_path(400 + k, p.path, p.ds)
+    log(f"  split batch: {len(probs)} instances, {sum(p.S for p in probs)} samples")
+    plain = [B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=400 + k))[0] for k, p in enumerate(probs)]
+    pbs = [B.ProblemBuffers(p, controller=400 + k) for k, p in enumerate(probs)]
+    for rep in range(2):
+        outs, _, _ = B.brmppi_solve_batch(ctx.h, pbs)
+        for k in range(len(probs)):
+            assert np.array_equal(outs[k], plain[k]), (rep, k)
+
+
 def test_served_alone_vs_mix(ctx):
     probs = W.config4_controllers(n_ctrl=40, seed=44)
     probs = [p.copy(S=min(p.S, 8192), T=min(p.T, 50)) for p in probs]
