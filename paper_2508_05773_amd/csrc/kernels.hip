@@ -1305,12 +1305,20 @@ static_assert(kUnit == 32 && kGroupUnits == 32, "a unit is half a wave; a group'
 // are not whole units), with the same canonical structure as the fused
 // epilogue.  Work item = (group of 1024 samples, d.rows_item rows): the
 // group's unit weights are recomputed from its 4 KB of costs (same code: same
-// values), the first row block also stores the group's (m_g, Z_g, Z2_g).  The
-// item's rows are taken in passes of 8: half-wave h of wave w takes row
-// 2 w + h of the pass, lane u of it unit u's 32 samples, and the loads of the
-// next pass are in flight while the current one is summed.  The unit sums are
-// merged in unit order by one thread per row, and the item is published once.
-// The last block of the instance merges the groups.
+// values), the first row block also stores the group's (m_g, Z_g, Z2_g).
+// Wave w owns the group's samples 256 w .. 256 w + 255 (units 8 w .. 8 w + 7)
+// and takes the item's rows 8 at a time: each row is read with one coalesced
+// 16-byte load per lane, the 8 rows go through a padded LDS tile of the wave,
+// and lane l then sums unit l % 8 of row l / 8 over its 32 samples in sample
+// order (the weights of its unit are held in registers).  The next 8 rows'
+// loads are in flight meanwhile.  The unit sums are merged in unit order by
+// one thread per row, and the item is published once.  The last block of the
+// instance merges the groups.
+constexpr int kRedRows = 8;                          // rows per wave and pass
+constexpr int kRedUnitStride = kUnit + 4;            // floats per unit segment in the tile (16 B pad)
+constexpr int kRedRowStride = 8 * kRedUnitStride;    // floats per row of a wave's tile
+static_assert(kRedRows * 8 == 64, "one (row, unit) pair per lane");
+
 __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restrict__ descs,
                                                      const Item* __restrict__ items, uint32_t n_items,
                                                      BatchCounters* __restrict__ ctr) {
@@ -1318,6 +1326,7 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
   __shared__ float s_mu[kGroupUnits], s_sig[kGroupUnits];
   __shared__ float4 s_up[kGroupUnits];
   __shared__ float s_R[kMaxRowsPerItem][kGroupUnits + 1];   // +1: row-wise reads hit distinct banks
+  __shared__ float4 s_T4[(kWThreads / 64) * kRedRows * kRedRowStride / 4];
   __shared__ float s_red[2 * (kWThreads / 64)];
   __shared__ float s_scale[kMaxWChunks];
   __shared__ double s_trig[kPlantLds];
@@ -1325,6 +1334,11 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
   const uint32_t t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   const float* s_gam = reinterpret_cast<const float*>(s_gam4);
+  float* s_T = reinterpret_cast<float*>(s_T4) + wid * (kRedRows * kRedRowStride);
+  // this lane's place in the wave's tile when storing (sample 4 lane of each
+  // row) and when summing (unit lu of row lr)
+  const uint32_t st_off = (uint32_t)(lane >> 3) * kRedUnitStride + 4 * (uint32_t)(lane & 7);
+  const uint32_t lu = (uint32_t)lane & 7u, lr = (uint32_t)lane >> 3;
   for (uint32_t it = 0;; ++it) {
     uint32_t ix;
     if (!next_item(it, n_items, ctr ? &ctr->r_next : nullptr, &s_slot, ix)) break;
@@ -1344,31 +1358,31 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     const uint32_t nu_g = min((uint32_t)kGroupUnits, d.n_units - gu0);
     const uint32_t r0 = rg * d.rows_item;
     const uint32_t nrow = min(d.rows_item, R - r0);
-    const uint32_t n_pass = (nrow + kRowsPerPass - 1) / kRowsPerPass;
 
-    // this lane's row in each pass and its unit; the first pass's applied
-    // inputs are loaded first so that their latency overlaps the weights
-    const uint32_t h = (uint32_t)lane >> 5, u = (uint32_t)lane & 31u;
-    const uint32_t rl = 2 * wid + h;
-    const float* __restrict__ colp = d.u_star + base + kUnit * u;
-    float4 uv[kUnit / 4];
-    {
-      const bool rv = (rl < nrow) && (u < nu_g);
-      const float* __restrict__ rowp = colp + (size_t)(rv ? r0 + rl : 0) * d.S_pad;
-#pragma unroll
-      for (int k = 0; k < kUnit / 4; ++k)
-        uv[k] = rv ? *reinterpret_cast<const float4*>(rowp + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-
-    // costs (thread t: samples 4t .. 4t + 3 of the group; unit t / 8)
+    // thread t: samples 4t .. 4t + 3 of the group (unit t / 8); S_pad is a
+    // multiple of 256, so a wave's samples are all inside the buffer or none
     const uint32_t s4 = base + 4 * t;
+    const bool sv = s4 < d.S_pad;
+    const float* __restrict__ colp = d.u_star + s4;
+    float4 q[kRedRows];
+    auto load_rows = [&](uint32_t p) {
+#pragma unroll
+      for (int j = 0; j < kRedRows; ++j) {
+        const uint32_t rr = p + (uint32_t)j;
+        q[j] = (sv && rr < nrow) ? *reinterpret_cast<const float4*>(colp + (size_t)(r0 + rr) * d.S_pad)
+                                 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    };
+    load_rows(0);    // in flight while the weights are formed
+
+    // costs and unit weights
     float jv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    if (s4 < d.S_pad) {
-      const float4 q = *reinterpret_cast<const float4*>(d.J + s4);
-      jv[0] = q.x;
-      jv[1] = q.y;
-      jv[2] = q.z;
-      jv[3] = q.w;
+    if (sv) {
+      const float4 c = *reinterpret_cast<const float4*>(d.J + s4);
+      jv[0] = c.x;
+      jv[1] = c.y;
+      jv[2] = c.z;
+      jv[3] = c.w;
     }
     float m = INFINITY;
 #pragma unroll
@@ -1398,31 +1412,38 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       }
       if (lane == 0) s_red[0] = mg;
     }
-    // unit row sums, in sample order, pass by pass
-    const float* gam = s_gam + kUnit * u;
-    for (uint32_t p = 0; p < n_pass; ++p) {
-      const uint32_t rp = p * kRowsPerPass + rl;          // row within the item
-      const bool rv = (rp < nrow) && (u < nu_g);
-      const uint32_t rn = rp + kRowsPerPass;              // next pass
-      const bool nv = (rn < nrow) && (u < nu_g);
-      float4 un[kUnit / 4];
-      const float* __restrict__ rowq = colp + (size_t)(nv ? r0 + rn : 0) * d.S_pad;
+    // the weights of the unit this lane sums
+    float gw[kUnit];
+    {
+      const float4* g4 = s_gam4 + (kUnit / 4) * (8 * (uint32_t)wid + lu);
 #pragma unroll
-      for (int k = 0; k < kUnit / 4; ++k)
-        un[k] = nv ? *reinterpret_cast<const float4*>(rowq + 4 * k) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (rv) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int k = 0; k < kUnit / 4; ++k) {
-          acc = unit_row_term(acc, gam[4 * k + 0], uv[k].x);
-          acc = unit_row_term(acc, gam[4 * k + 1], uv[k].y);
-          acc = unit_row_term(acc, gam[4 * k + 2], uv[k].z);
-          acc = unit_row_term(acc, gam[4 * k + 3], uv[k].w);
-        }
-        s_R[rp][u] = acc;
+      for (int k = 0; k < kUnit / 4; ++k) {
+        const float4 w = g4[k];
+        gw[4 * k + 0] = w.x;
+        gw[4 * k + 1] = w.y;
+        gw[4 * k + 2] = w.z;
+        gw[4 * k + 3] = w.w;
       }
+    }
+    // unit row sums, in sample order, 8 rows per pass
+    for (uint32_t p = 0; p < nrow; p += kRedRows) {
 #pragma unroll
-      for (int k = 0; k < kUnit / 4; ++k) uv[k] = un[k];
+      for (int j = 0; j < kRedRows; ++j)
+        *reinterpret_cast<float4*>(s_T + j * kRedRowStride + st_off) = q[j];
+      load_rows(p + kRedRows);
+      __builtin_amdgcn_wave_barrier();
+      const float4* u4 = reinterpret_cast<const float4*>(s_T + lr * kRedRowStride + lu * kRedUnitStride);
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kUnit / 4; ++k) {
+        const float4 u = u4[k];
+        acc = unit_row_term(acc, gw[4 * k + 0], u.x);
+        acc = unit_row_term(acc, gw[4 * k + 1], u.y);
+        acc = unit_row_term(acc, gw[4 * k + 2], u.z);
+        acc = unit_row_term(acc, gw[4 * k + 3], u.w);
+      }
+      if (p + lr < nrow) s_R[p + lr][8 * wid + lu] = acc;
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     if (rg == 0 && t == 0) {
