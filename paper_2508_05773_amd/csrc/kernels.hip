@@ -489,6 +489,16 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const uint32_t S_pad = d.S_pad;
   float* __restrict__ ustar = d.u_star;
   const float* __restrict__ unom = d.u_nom_in;
+  // The progress rate is not projected, so psi of the next step is known as
+  // soon as a step's inputs are drawn.  With eight lanes per sample (the form
+  // for few samples, where one wave per SIMD leaves every latency exposed) the
+  // next step's reference point (an LDS path lookup) and nominal inputs are
+  // fetched one step ahead, off the dependency chain of the projection and the
+  // state update; the other forms have waves enough to hide them and fewer
+  // registers to spare.  Both orders compute the same values.
+  constexpr bool kAhead = (G == 8);
+  RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  float un_j = unom[0], un_w = unom[1], un_nu = unom[2];
 
   // precomputed normals of the next PF steps (a register queue: slot 0 is
   // the current step, loads run PF steps ahead of their use)
@@ -555,11 +565,28 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
         for (int j = 0; j < NSL; ++j) e_o[j] = eps[5 + j];   // G == 1: slot j is obstacle j
       }
     }
-    float uj = unom[3 * tau + 0] + P.sigma_j * e_in[0];
-    float uw = unom[3 * tau + 1] + P.sigma_w * e_in[1];
-    const float unu = unom[3 * tau + 2] + P.sigma_nu * e_in[2];
-
-    const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+    if constexpr (!kAhead) {
+      un_j = unom[3 * tau + 0];
+      un_w = unom[3 * tau + 1];
+      un_nu = unom[3 * tau + 2];
+    }
+    float uj = un_j + P.sigma_j * e_in[0];
+    float uw = un_w + P.sigma_w * e_in[1];
+    const float unu = un_nu + P.sigma_nu * e_in[2];
+    if constexpr (kAhead) {
+      if (tau + 1 < d.T) {
+        un_j = unom[3 * tau + 3];
+        un_w = unom[3 * tau + 4];
+        un_nu = unom[3 * tau + 5];
+      }
+    }
+    const float psi_next = psi + Ts * unu;
+    RefPoint rf_next;
+    if constexpr (kAhead) {
+      rf_next = reference(phi0 + psi_next * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+    } else if (tau > 0) {
+      rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+    }
     const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
     const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
     const float tn = tg.sd * rcp(tg.cd);    // |delta| stays far from pi/2: cos > 0
@@ -675,7 +702,8 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float nth1 = th1 + Ts * vkd;
     const float nth2 = th2 + Ts * v * inv_l2 * Aw2;
     const float ndl = dl + Ts * uw;
-    psi += Ts * unu;
+    psi = psi_next;
+    if constexpr (kAhead) rf = rf_next;
     px = npx;
     py = npy;
     v = nv;
@@ -684,8 +712,8 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     th2 = nth2;
     dl = ndl;
   }
-  const RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
-  float rN = tracking_cost(P, rf, px, py, th1, th2);
+  if constexpr (!kAhead) rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
   if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
   J += (double)rN;
   float Jf = (float)J;
