@@ -972,14 +972,16 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
   float pre[kPre];
 #pragma unroll
   for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? d.rpart[(size_t)k * R + r0] : 0.0f;
-  float mloc = INFINITY;
-  for (uint32_t c = threadIdx.x; c < nW; c += nt) {
+  // this thread's first group partial is loaded once, for the minimum and the sums
+  const float4 w_first = threadIdx.x < nW ? d.wpart[threadIdx.x] : make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
+  float mloc = w_first.x;
+  for (uint32_t c = threadIdx.x + nt; c < nW; c += nt) {
     mloc = fminf(mloc, d.wpart[c].x);
   }
   const float m = block_min(mloc, s_red);
   float zl = 0.0f, z2l = 0.0f;
   for (uint32_t c = threadIdx.x; c < nW; c += nt) {
-    const float4 w = d.wpart[c];
+    const float4 w = c == threadIdx.x ? w_first : d.wpart[c];
     const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
     s_scale[c] = sc;
     zl += sc * w.y;
@@ -1101,7 +1103,10 @@ __device__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint
     s_sig[t] = merge_scale(up.x, mg, d.inv_lambda);
   }
   __syncthreads();
-  if (t == 0) {
+  // the group's (Z, Z2), on the first thread of a wave without a row when there
+  // is one, so that it overlaps the row sums instead of preceding them
+  const uint32_t tz = ((R + 63u) & ~63u) < nt ? ((R + 63u) & ~63u) : 0u;
+  if (t == tz) {
     float z, z2;
     group_sums(s_up, s_sig, nu_g, z, z2);
     d.wpart[grp] = make_float4(mg, z, z2, 0.0f);
@@ -1474,7 +1479,7 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    if (rg == 0 && t == 0) {
+    if (rg == 0 && t == kWThreads - 1) {   // a thread without a row: overlaps the row merges
       float z, z2;
       group_sums(s_up, s_sig, nu_g, z, z2);
       d.wpart[grp] = make_float4(s_red[0], z, z2, 0.0f);
