@@ -379,24 +379,31 @@ __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, in
 }
 
 // sine and cosine of the four angles a step needs (th1, th1 - th2, delta and
-// the reference heading), one sincos per lane for G >= 4, then broadcast
+// the reference heading), one pair per lane for G >= 4, then broadcast.  The
+// hardware sine and cosine (absolute error of order 1e-6 over the angles a
+// rollout reaches) keep the library's range reduction off the step's chain.
 struct StepTrig {
   float s1, c1, sp, cp, sd, cd, sr, cr;
 };
+
+__device__ __forceinline__ void step_sincos(float x, float* s, float* c) {
+  *s = __sinf(x);
+  *c = __cosf(x);
+}
 
 template <int G>
 __device__ __forceinline__ StepTrig step_trig(int g, float a0, float a1, float a2, float a3) {
   StepTrig t;
   if constexpr (G == 1) {
-    sincosf(a0, &t.s1, &t.c1);
-    sincosf(a1, &t.sp, &t.cp);
-    sincosf(a2, &t.sd, &t.cd);
-    sincosf(a3, &t.sr, &t.cr);
+    step_sincos(a0, &t.s1, &t.c1);
+    step_sincos(a1, &t.sp, &t.cp);
+    step_sincos(a2, &t.sd, &t.cd);
+    step_sincos(a3, &t.sr, &t.cr);
   } else if constexpr (G == 2) {
     // lane g: angles g and g + 2
     float s0, c0, s2, c2;
-    sincosf(g == 0 ? a0 : a1, &s0, &c0);
-    sincosf(g == 0 ? a2 : a3, &s2, &c2);
+    step_sincos(g == 0 ? a0 : a1, &s0, &c0);
+    step_sincos(g == 0 ? a2 : a3, &s2, &c2);
     t.s1 = group_bcast<2, 0>(s0);
     t.c1 = group_bcast<2, 0>(c0);
     t.sp = group_bcast<2, 1>(s0);
@@ -410,7 +417,7 @@ __device__ __forceinline__ StepTrig step_trig(int g, float a0, float a1, float a
     const int k = g & 3;
     const float a = k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
     float sa, ca;
-    sincosf(a, &sa, &ca);
+    step_sincos(a, &sa, &ca);
     t.s1 = group_bcast<G, 0>(sa);
     t.c1 = group_bcast<G, 0>(ca);
     t.sp = group_bcast<G, 1>(sa);
@@ -726,23 +733,31 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 
 
 // ---------------------------------------------------------------------------
-// Noise: every (sample, step, Philox block) in parallel -> [tau][k][S_pad]
+// Noise: every (sample, step) in parallel, all its Philox blocks in one thread
+// (independent chains the scheduler interleaves) -> [tau][k][S_pad]
 // ---------------------------------------------------------------------------
+constexpr int kMaxPhiloxBlocks = (5 + BRMPPI_MAX_OBS + 3) / 4;
+
 __global__ __launch_bounds__(256) void k_noise(const char* __restrict__ descs, uint32_t stride, uint32_t nb) {
-  // blockIdx.z = (update u of a run of consecutive descriptors) * nb + Philox block
-  const uint32_t u = blockIdx.z / nb, b = blockIdx.z % nb;
-  const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)u * stride);
+  // blockIdx.z = update u of a run of consecutive descriptors
+  const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)blockIdx.z * stride);
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t tau = blockIdx.y;
   if (s >= d.S) return;
-  uint32_t r[4];
-  float e[4];
-  philox4x32_10(s, tau, b, d.instance, d.seed_lo, d.seed_hi, r);
-  box_muller4(r, e);
+  float* __restrict__ out = d.noise + (size_t)tau * d.n_normals * d.S_pad + s;
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    const uint32_t kk = 4 * b + k;
-    if (kk < d.n_normals) d.noise[((size_t)tau * d.n_normals + kk) * d.S_pad + s] = e[k];
+  for (int b = 0; b < kMaxPhiloxBlocks; ++b) {
+    if ((uint32_t)b < nb) {
+      uint32_t r[4];
+      float e[4];
+      philox4x32_10(s, tau, (uint32_t)b, d.instance, d.seed_lo, d.seed_hi, r);
+      box_muller4(r, e);
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t kk = 4 * (uint32_t)b + k;
+        if (kk < d.n_normals) out[(size_t)kk * d.S_pad] = e[k];
+      }
+    }
   }
 }
 
@@ -1628,8 +1643,8 @@ int rollout_blocks_per_cu(int bucket, int variant, uint32_t block) {
 hipError_t launch_noise(const SolveDesc* first, size_t stride, uint32_t count, uint32_t S, uint32_t T,
                         uint32_t n_normals, hipStream_t stream) {
   const uint32_t nb = (n_normals + 3) / 4;
-  if (count == 0 || nb == 0) return hipSuccess;
-  const dim3 grid((S + 255) / 256, T, nb * count);
+  if (count == 0 || nb == 0 || nb > (uint32_t)kMaxPhiloxBlocks) return count == 0 || nb == 0 ? hipSuccess : hipErrorInvalidValue;
+  const dim3 grid((S + 255) / 256, T, count);
   hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, stream, reinterpret_cast<const char*>(first), (uint32_t)stride, nb);
   return hipGetLastError();
 }
