@@ -143,21 +143,30 @@ def main():
             note("autotuning launch shapes")
             B.brmppi_autotune(h)
         shape = json.load(open(tune_file)).get("plain_8_1")   # 8-obstacle bucket, S <= 8192
-    ctx.set_path(0, prob.path, prob.ds)
-    pb = B.ProblemBuffers(prob, controller=0)
+    # the value is timed on a context that records no events (a pair of HIP
+    # events around every launch puts stream markers between the kernels and
+    # costs about 9 us per update); the same loop then runs on the profiling
+    # context, which times every rollout launch with HIP events on its stream
+    ctx2 = B.Context(arena_bytes=3 << 30, n_streams=2, max_controllers=600, profile=False,
+                     autotune_cache=tune_file)
 
-    # ---- warm-up, then the timed closed loop from the start state ----
-    if args.warmup > 0:
-        B.brmppi_closed_loop(h, pb, args.warmup, want_x=False, want_u=False)
-    B.brmppi_profile_reset(h)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.brmppi_closed_loop(h, pb, args.steps, want_x=False, want_u=False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = B.brmppi_profile_read(h)
-    x_end = B.brmppi_get_state(h, 0)
+    def timed_loop(c):
+        c.set_path(0, prob.path, prob.ds)
+        pb = B.ProblemBuffers(prob, controller=0)
+        # ---- warm-up, then the timed closed loop from the start state ----
+        if args.warmup > 0:
+            B.brmppi_closed_loop(c.h, pb, args.warmup, want_x=False, want_u=False)
+        B.brmppi_profile_reset(c.h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.brmppi_closed_loop(c.h, pb, args.steps, want_x=False, want_u=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, B.brmppi_get_state(c.h, 0)
+
+    wall, x_end = timed_loop(ctx2)
     value = S * T * args.steps / wall
+    wall_prof, _ = timed_loop(ctx)
+    prof = B.brmppi_profile_read(h)
     roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
     # the closed loop draws the normals of several updates per noise launch
     noise_ms = prof["noise"]["ms"] / args.steps if prof["noise"]["count"] else 0.0
@@ -184,6 +193,7 @@ def main():
                                "ellipses, 200 receding-horizon updates, device-resident",
                    "S": S, "T": T, "n_obs": n_obs, "updates": args.steps},
         "solves_per_s": args.steps / wall,
+        "ms_per_step_with_launch_events": wall_prof * 1e3 / args.steps,
         "final_state_finite": bool(np.all(np.isfinite(x_end))),
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -204,13 +214,11 @@ def main():
         out["large"] = large_leg(B, W, ctx, tune_file if not args.no_autotune else None)
     ctx.close()
     if legs - {"large"}:
-        # the other legs run on a context without kernel timing: with timing on,
-        # a batch is launched directly instead of replayed from its HIP graph,
-        # and every timed launch records two events
-        ctx2 = B.Context(arena_bytes=3 << 30, n_streams=2, max_controllers=600, profile=False,
-                         autotune_cache=tune_file)
+        # the other legs run on the context without kernel timing: with timing
+        # on, a batch is launched directly instead of replayed from its HIP
+        # graph, and every timed launch records two events
         out.update(extras(args, B, W, ctx2, prob, legs))
-        ctx2.close()
+    ctx2.close()
 
     if not args.no_cpu:
         note("cpu baseline (oracle)")
