@@ -63,7 +63,15 @@ def rollout_flops(S: int, T: int, n_obs: int, hitch=True, guided=True, noise_in_
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """hash of the kernel source's code: line comments, trailing blanks and
+    empty lines do not count, so that a comment edit keeps the measured
+    traffic valid"""
+    code = []
+    for line in open(KERNEL_SRC, encoding="utf-8").read().splitlines():
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def load_traffic():
@@ -170,7 +178,7 @@ def main():
     roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
     # the closed loop draws the normals of several updates per noise launch
     noise_ms = prof["noise"]["ms"] / args.steps if prof["noise"]["count"] else 0.0
-    # variants 1-3 draw the normals in the separate noise kernel: the rollout
+    # variants 1-4 draw the normals in the separate noise kernel: the rollout
     # kernel's own algorithmic work then excludes the Box-Muller flops
     noise_in_kernel = prof["noise"]["count"] == 0
     flops = rollout_flops(S, T, n_obs, noise_in_kernel=noise_in_kernel)

@@ -980,7 +980,7 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
   const uint32_t nt = blockDim.x;
   const bool plant = (d.flags & BRMPPI_ADVANCE_PLANT) != 0;
   if (plant) plant_prep(d, s_plant);   // overlaps the merge
-  // the first 8 chunk partials of this thread's first row, loaded before the
+  // the first 8 group partials of this thread's first row, loaded before the
   // merge's barriers so that their latency overlaps them
   constexpr int kPre = 8;
   const uint32_t r0 = threadIdx.x;

@@ -259,8 +259,8 @@ struct ServedBatch {
 };
 
 // rollout launch shape: block size and variant (0 = one lane per sample,
-// in-kernel noise; 1 = one lane, precomputed noise; 2 / 3 = two / four lanes
-// per sample, precomputed noise).  No shape changes any result bit.
+// in-kernel noise; 1 = one lane, precomputed noise; 2 / 3 / 4 = two / four /
+// eight lanes per sample, precomputed noise).  No shape changes any result bit.
 struct LaunchShape {
   uint32_t block = 128;
   int variant = 0;
