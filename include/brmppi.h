@@ -126,8 +126,9 @@ typedef struct {
 } brmppi_params;
 
 /* Obstacle (Sec. IV-C, eq. (16)): centre (cx, cy) at t = 0, semi-axes (mx, my),
- * orientation heading, exponent e (only e == 2 is implemented), constant
- * velocity (vx, vy) for the prediction of Assumption 2. */
+ * orientation heading, super-ellipse exponent e (2 or 4; other values are
+ * EINVAL), constant velocity (vx, vy) for the prediction of Assumption 2.  The
+ * semi-axes are inflated by params->r_disc. */
 typedef struct { float cx, cy, mx, my, heading, e, vx, vy; } brmppi_obstacle;
 
 /* One control update (the finite-horizon problem of eq. (8) plus MPPI inputs). */
@@ -197,9 +198,12 @@ int brmppi_solve_ex(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outpu
                     brmppi_stats* st);
 
 /* ---- batched solve (blocking) ------------------------------------------- */
-/* n independent updates (distinct controllers) in one persistent-kernel
- * launch captured in a HIP graph.  u_outs[i] receives T_i*3 floats; st may be
- * NULL or an array of n.  Each instance's result equals its plain solve. */
+/* n independent updates (distinct controllers) together: persistent rollout
+ * launches over a tile list (one per constraint bucket present; a bucket too
+ * small to fill the device joins the next heavier one), then one persistent
+ * reduce over every instance, captured in a HIP graph and replayed while the
+ * batch keeps its shape.  u_outs[i] receives T_i*3 floats; st may be NULL or
+ * an array of n.  Each instance's result equals its plain solve, bitwise. */
 int brmppi_solve_batch(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n, float* const* u_outs,
                        brmppi_stats* st);
 
@@ -230,12 +234,14 @@ int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_upda
                        float* u_applied);
 
 /* ---- launch shapes / profiling ------------------------------------------ */
-/* Time the rollout for each candidate launch shape (block size and variant:
- * samples per wave, noise drawn in the kernel or by a separate parallel
- * kernel) on synthetic problems and keep the fastest per constraint bucket
- * (0, <=2, <=8, <=16, <=32 obstacles) and sample-count class (<=2048, <=8192,
- * <=32768, more), plus the block size of the batched persistent kernel;
- * writes the JSON cache named in the config (if any).  Shapes never change a
+/* Time each candidate launch shape (block size and variant: lanes per
+ * sample, noise drawn in the kernel or by a separate parallel kernel) on
+ * synthetic problems with a 48-step horizon, rollout plus reduction as a plain
+ * solve runs them, and keep the fastest per constraint bucket (0, <=2, <=8,
+ * <=16, <=32 obstacles) and sample-count class (<=2048, <=8192, <=32768,
+ * more), plus the block size of the batched persistent kernel; a shape whose
+ * tiles reduce themselves wins ties within 2 %.  Writes the JSON cache named
+ * in the config (if any), with every candidate's time.  Shapes never change a
  * result bit. */
 int brmppi_autotune(brmppi_ctx* ctx);
 /* Force a rollout launch shape for every plain and batched launch: block size
@@ -246,9 +252,12 @@ int brmppi_autotune(brmppi_ctx* ctx);
  * 0 or 1).  block 0 restores the tuned/default choice.  EINVAL for a block
  * outside 64..256 or not a multiple of 64, or a variant above 4. */
 int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant);
-/* Kernel timings accumulated under BRMPPI_CTX_PROFILE (ms totals and counts):
+/* Kernel timings accumulated under BRMPPI_CTX_PROFILE (every kernel of the
+ * blocking calls) or BRMPPI_CTX_PROFILE_ROLLOUT (rollout and noise only), from
+ * HIP events on the launching stream (ms totals and launch counts):
  * out[0..1] rollout, out[2..3] reduce (weights + average + shift + plant),
- * out[4..5] noise. */
+ * out[4..5] noise.  A profiling context launches batches directly instead of
+ * replaying their graph. */
 int brmppi_profile_read(brmppi_ctx* ctx, double out[6]);
 int brmppi_profile_reset(brmppi_ctx* ctx);
 
