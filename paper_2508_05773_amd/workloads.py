@@ -341,6 +341,46 @@ def config2(update: int = 0) -> Problem:
                    instance=0, name="c2", meta={"L": L})
 
 
+# Values the paper prints for its experiments (Sec. V and its table of parking
+# results).  tests/test_paper_constants.py checks them against the cited
+# fixture tests/golden/paper_sec5.json.
+PAPER_VEHICLE = dict(l1=3.23, l2=2.9, lh=1.15)     # tractor wheelbase, trailer length, hitch length [m]
+PAPER_HORIZON_STEPS = 120                          # H
+PAPER_HORIZON_S = 4.8                              # H Ts [s]
+PAPER_ROLLOUTS = 5000
+PAPER_OBSTACLES = 8
+PAPER_TIME_MS = {"forward": {"mppi": 3.20, "mppi_col": 13.00, "br_mppi": 9.92},
+                 "backward": {"mppi": 3.00, "mppi_col": 14.00, "br_mppi": 9.75}}
+
+
+def paper_shape(flags: int = 0) -> Problem:
+    """The configuration of the paper's timing comparison (Sec. V): 5000
+    rollouts over H = 120 steps of 0.04 s with the Sec. V vehicle and eight
+    obstacles on the reverse-parking scene: seven parked vehicles as e = 4
+    super-ellipses along the bay and a pedestrian (e = 2, a disc of 0.5 m)
+    crossing the bay entrance at 1.2 m/s.  The footprint disc radius is half the
+    2.5 m trailer width."""
+    rng = np.random.default_rng(6)
+    path, L = path_c2()
+    x0 = _start_state(path)
+    parked = bay_obstacles(rng, path)[:7].copy()
+    parked[:, 5] = 4.0
+    # the pedestrian starts 4 m to the side of the bay entrance and walks across it
+    n = path.shape[0]
+    k0 = n - 1 - int(round(20.0 / 0.1))
+    tx, ty = float(path[k0 + 1, 0] - path[k0, 0]), float(path[k0 + 1, 1] - path[k0, 1])
+    tn = math.hypot(tx, ty)
+    nx, ny = -ty / tn, tx / tn
+    ped = np.array([[path[k0, 0] - 4.0 * nx, path[k0, 1] - 4.0 * ny, 0.5, 0.5, 0.0, 2.0, 1.2 * nx, 1.2 * ny]],
+                   dtype=np.float32)
+    obs = np.vstack([parked, ped]).astype(np.float32)
+    T = PAPER_HORIZON_STEPS
+    params = make_params(PAPER_HORIZON_S / PAPER_HORIZON_STEPS, r_disc=1.25, **PAPER_VEHICLE)
+    return Problem(S=PAPER_ROLLOUTS, T=T, x0=x0, u_nom=np.zeros((T, 3), np.float32), obstacles=obs,
+                   path=path, ds=0.1, params=params, lam=1.0, seed=6, instance=0, flags=flags,
+                   name="paper", meta={"L": L})
+
+
 def config3(n_instances: int = 64, seed: int = 3) -> list:
     """64 uneven instances: S in {1024..16384}, T in [20, 80], 0-16 obstacles."""
     rng = np.random.default_rng(seed)

@@ -195,6 +195,18 @@ def test_c2_full_size(ctx):
     compare(p, g, o, "c2")
 
 
+@pytest.mark.parametrize("flags", [0, W.FLAG_GUIDANCE_OFF | W.FLAG_COLLISION_PENALTY])
+def test_paper_shape_full_size(ctx, flags):
+    """the paper's experiment shape (Sec. V): S = 5000, T = 120, its vehicle,
+    seven e = 4 parked vehicles and a crossing e = 2 pedestrian; BR-MPPI and
+    the collision-penalty baseline, every sample against the oracle"""
+    from oracle import oracle as O
+    p = W.paper_shape(flags=flags)
+    g = run_gpu(ctx, p, controller=27)
+    o = O.solve(p, nthreads=NTHREADS)
+    compare(p, g, o, f"paper shape flags={flags}")
+
+
 def test_c5_sampled(ctx):
     """S = 65536, T = 100, 32 obstacles: per-sample costs of 512 sampled rollouts,
     and the weight identities (sum w = 1 via Z, J_min equal) at full size"""
