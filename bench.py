@@ -358,6 +358,10 @@ def large_leg(B, W, ctx, tune_file):
         shape = json.load(open(tune_file)).get("plain_32_3") if tune_file else None
     except (OSError, ValueError):
         pass
+    # a table entry with precomputed normals falls back to the one-lane form
+    # with in-kernel normals when the noise buffer does not fit: no noise launch
+    if shape and noise_in_kernel and shape[1] != 0:
+        shape = [shape[0], 0]
     return {"workload": "S=65536, T=100, 32 ellipses, three-piece spline path with cusps",
             "launch_shape": {"block_variant": shape},
             "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),

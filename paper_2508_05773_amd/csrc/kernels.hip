@@ -81,6 +81,20 @@ __device__ __forceinline__ float wrap_angle(float x) { return x - kTwoPi * rintf
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Loads and stores through global-address-space pointers.  Pointers read from
+// a descriptor are generic, and a generic (flat) access also counts against
+// the LDS/scalar wait counter: every wait for an LDS or scalar result would
+// then wait for the step-ahead HBM loads as well.
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float gld(const float* p) {
+  return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ float4 gld4(const float4* p) {
+  const gvec4 v = *(const __attribute__((address_space(1))) gvec4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst(float* p, float v) { *(__attribute__((address_space(1))) float*)p = v; }
+
 // Obstacle staged in LDS: centre relative to the tile origin, velocity; for
 // e = 2 the shape matrix Q = R' diag((mx+r)^-2, (my+r)^-2) R of eq. (16), for
 // e = 4 (e4 = 1) the rotation (co, so) into the obstacle frame and the
@@ -111,14 +125,14 @@ __device__ __forceinline__ RefPoint reference(float f, int k0, int n_path, const
     t = 1.0f;
   }
   if (!(t >= 0.0f)) t = 0.0f;
-  float4 A, B;
+  // the window in LDS is read unconditionally (nw >= 2, so the clamped index
+  // is in range); a point outside it is fetched from HBM instead
   const int li = gi - w0;
-  if (li >= 0 && li + 1 < nw) {
-    A = spath[li];
-    B = spath[li + 1];
-  } else {
-    A = gpath[gi];
-    B = gpath[gi + 1];
+  const int lc = min(max(li, 0), nw - 2);
+  float4 A = spath[lc], B = spath[lc + 1];
+  if (!(li >= 0 && li + 1 < nw)) {
+    A = gld4(gpath + gi);
+    B = gld4(gpath + gi + 1);
     A.x -= ox;
     A.y -= oy;
     B.x -= ox;
@@ -349,11 +363,6 @@ __device__ __forceinline__ Acc5 virtual_tree(Leaf& leaf) {
   }
 }
 
-// normals k of (s, tau) in the noise buffer [tau][k][S_pad]
-__device__ __forceinline__ const float* noise_row(const SolveDesc& d, uint32_t tau, uint32_t k) {
-  return d.noise + ((size_t)tau * d.n_normals + k) * d.S_pad;
-}
-
 // Collision-penalty baseline (the paper's second MPPI baseline, Sec. V; its
 // form is not given): sum_o max(0, -h_o)^2 with h_o the obstacle function of
 // eq. (16) (e = 2 or 4) at the current position and time, in obstacle order
@@ -505,54 +514,51 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // registers to spare.  Both orders compute the same values.
   constexpr bool kAhead = (G == 8);
   RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
-  float un_j = unom[0], un_w = unom[1], un_nu = unom[2];
+  float un_j = gld(unom + 0), un_w = gld(unom + 1), un_nu = gld(unom + 2);
 
-  // precomputed normals of the next PF steps (a register queue: slot 0 is
-  // the current step, loads run PF steps ahead of their use)
-  constexpr int PF = PRE ? kNoisePrefetch : 1;
+  // Precomputed normals are loaded PF = 2 steps ahead into a queue of two
+  // slots: step tau reads slot tau % 2 and refills it with step tau + 2.  The
+  // loop is unrolled by two so that the slot is a compile-time index (no
+  // register moves, which would wait for the loads in flight).  Every load is
+  // in range (step and row indices clamped), so none needs a branch; rows
+  // past the instance's own (obstacles o >= n_obs, unguided instances) feed
+  // only rows whose terms are zeroed or unused.
+  static_assert(!PRE || kNoisePrefetch == 2, "two queue slots");
+  constexpr int PF = PRE ? 2 : 1;
   float nx_in[PF][3], nx_h[PF][NH], nx_o[PF][NSL];
+  const uint32_t n_rows = d.n_normals;
+  const size_t step_stride = (size_t)n_rows * S_pad;
   auto load_normals = [&](uint32_t tau, int q) {
     if constexpr (PRE) {
+      const float* __restrict__ base = d.noise + (size_t)tau * step_stride + s;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) nx_in[q][k] = noise_row(d, tau, k)[s];
-      if (guided) {
+      for (int k = 0; k < 3; ++k) nx_in[q][k] = gld(base + (size_t)k * S_pad);
 #pragma unroll
-        for (int k = 0; k < NH; ++k) nx_h[q][k] = noise_row(d, tau, 3 + hk0 + k)[s];
+      for (int k = 0; k < NH; ++k)
+        nx_h[q][k] = gld(base + (size_t)min((uint32_t)(3 + hk0 + k), n_rows - 1) * S_pad);
 #pragma unroll
-        for (int j = 0; j < NSL; ++j) {
-          const int o = g + G * j;
-          nx_o[q][j] = (o < n_obs) ? noise_row(d, tau, 5 + o)[s] : 0.0f;
-        }
-      }
+      for (int j = 0; j < NSL; ++j)
+        nx_o[q][j] = gld(base + (size_t)min((uint32_t)(5 + g + G * j), n_rows - 1) * S_pad);
     }
   };
   if constexpr (PRE) {
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-      if ((uint32_t)q < d.T) load_normals((uint32_t)q, q);
+    load_normals(0u, 0);
+    load_normals(min(1u, d.T - 1), 1);
   }
 
-  for (uint32_t tau = 0; tau < d.T; ++tau) {
+  auto step = [&](const uint32_t tau, auto SLOT) __attribute__((always_inline)) {
+    constexpr int q = decltype(SLOT)::value;
     // --- noise: normals 0..2 perturb the inputs, 3 and 4 the hitch rows'
     // auxiliary inputs, 5 + o obstacle o's ---
     float e_in[3], e_h[NH], e_o[NSL];
     if constexpr (PRE) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) e_in[k] = nx_in[0][k];
+      for (int k = 0; k < 3; ++k) e_in[k] = nx_in[q][k];
 #pragma unroll
-      for (int k = 0; k < NH; ++k) e_h[k] = nx_h[0][k];
+      for (int k = 0; k < NH; ++k) e_h[k] = nx_h[q][k];
 #pragma unroll
-      for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[0][j];
-#pragma unroll
-      for (int q = 0; q + 1 < PF; ++q) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) nx_in[q][k] = nx_in[q + 1][k];
-#pragma unroll
-        for (int k = 0; k < NH; ++k) nx_h[q][k] = nx_h[q + 1][k];
-#pragma unroll
-        for (int j = 0; j < NSL; ++j) nx_o[q][j] = nx_o[q + 1][j];
-      }
-      if (tau + PF < d.T) load_normals(tau + PF, PF - 1);
+      for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[q][j];
+      load_normals(min(tau + 2, d.T - 1), q);
     } else {
       float eps[4 * NBMAX];
 #pragma unroll
@@ -573,19 +579,18 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       }
     }
     if constexpr (!kAhead) {
-      un_j = unom[3 * tau + 0];
-      un_w = unom[3 * tau + 1];
-      un_nu = unom[3 * tau + 2];
+      un_j = gld(unom + 3 * tau + 0);
+      un_w = gld(unom + 3 * tau + 1);
+      un_nu = gld(unom + 3 * tau + 2);
     }
     float uj = un_j + P.sigma_j * e_in[0];
     float uw = un_w + P.sigma_w * e_in[1];
     const float unu = un_nu + P.sigma_nu * e_in[2];
     if constexpr (kAhead) {
-      if (tau + 1 < d.T) {
-        un_j = unom[3 * tau + 3];
-        un_w = unom[3 * tau + 4];
-        un_nu = unom[3 * tau + 5];
-      }
+      const uint32_t tn = min(tau + 1, d.T - 1);
+      un_j = gld(unom + 3 * tn + 0);
+      un_w = gld(unom + 3 * tn + 1);
+      un_nu = gld(unom + 3 * tn + 2);
     }
     const float psi_next = psi + Ts * unu;
     RefPoint rf_next;
@@ -690,9 +695,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
     if (store) {
       if (d.ustar_global) {
-        ustar[(size_t)(3 * tau + 0) * S_pad + s] = uj;
-        ustar[(size_t)(3 * tau + 1) * S_pad + s] = uw;
-        ustar[(size_t)(3 * tau + 2) * S_pad + s] = unu;
+        gst(ustar + (size_t)(3 * tau + 0) * S_pad + s, uj);
+        gst(ustar + (size_t)(3 * tau + 1) * S_pad + s, uw);
+        gst(ustar + (size_t)(3 * tau + 2) * S_pad + s, unu);
       }
       if (s_u) {
         s_u[(3 * tau + 0) * lds_stride + t_local] = uj;
@@ -718,6 +723,14 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     th1 = nth1;
     th2 = nth2;
     dl = ndl;
+  };
+  if constexpr (PRE) {
+    for (uint32_t tau = 0; tau < d.T; tau += 2) {
+      step(tau, std::integral_constant<int, 0>{});
+      if (tau + 1 < d.T) step(tau + 1, std::integral_constant<int, 1>{});
+    }
+  } else {
+    for (uint32_t tau = 0; tau < d.T; ++tau) step(tau, std::integral_constant<int, 0>{});
   }
   if constexpr (!kAhead) rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T

@@ -219,8 +219,10 @@ uint32_t reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu) {
   return kRowsPerPass;
 }
 
-// largest precomputed-noise buffer a plain solve may take
-constexpr size_t kMaxNoiseBytes = size_t(512) << 20;
+// largest precomputed-noise buffer a plain solve may take; it is also held to
+// half of the context's arena.  Beyond it the solve draws its normals in the
+// rollout kernel (one lane per sample).
+constexpr size_t kMaxNoiseBytes = size_t(2) << 30;
 // closed loop: normals of up to this many bytes are drawn per noise launch
 constexpr size_t kClosedLoopNoiseBytes = size_t(256) << 20;
 
@@ -437,7 +439,7 @@ LaunchShape plain_shape(brmppi_ctx* ctx, const brmppi_problem& p) {
   LaunchShape s = ctx->forced.block ? ctx->forced : ctx->shape[bucket_index(bucket)][s_class(p.S)];
   if (bucket == 0 && s.variant > 1) s.variant = 1;        // unguided: one lane per sample
   const size_t noise = (size_t)normals_per_step(p) * p.T * round_up(p.S, 256) * sizeof(float);
-  if (variant_pre(s.variant) && noise > kMaxNoiseBytes) s.variant = 0;
+  if (variant_pre(s.variant) && noise > std::min(kMaxNoiseBytes, ctx->arena.size() / 2)) s.variant = 0;
   return s;
 }
 

@@ -234,6 +234,33 @@ def test_default_launch_table_in_effect():
         c.close()
 
 
+def test_large_noise_buffer():
+    """S = 65536, T = 100, 32 obstacles: 970 MB of precomputed normals.  With a
+    3 GiB arena the four-lane form draws them in the noise kernel; with a 1 GiB
+    arena (half of it is the limit) the same request falls back to in-kernel
+    normals.  Both give the bits of the one-lane in-kernel solve."""
+    p = W.config5()
+    runs = {}
+    for arena, shape in ((3 << 30, (256, 3)), (3 << 30, (128, 0)), (1 << 30, (256, 3))):
+        c = B.Context(arena_bytes=arena, n_streams=1, max_controllers=4, flags_extra=B.CTX_PROFILE_ROLLOUT)
+        try:
+            log(f"  c5 arena={arena >> 30} GiB shape={shape}")
+            c.set_path(0, p.path, p.ds)
+            B.brmppi_set_launch(c.h, *shape)
+            g = B.brmppi_solve_ex(c.h, B.ProblemBuffers(p, controller=0), want_J=True)
+            prof = B.brmppi_profile_read(c.h)
+            runs[(arena, shape)] = (g, prof["noise"]["count"])
+        finally:
+            c.close()
+    ref, n_ref = runs[(3 << 30, (128, 0))]
+    assert n_ref == 0
+    assert runs[(3 << 30, (256, 3))][1] == 1
+    assert runs[(1 << 30, (256, 3))][1] == 0
+    for key, (g, _) in runs.items():
+        assert np.array_equal(g["J"], ref["J"]), key
+        assert np.array_equal(g["U_new"], ref["U_new"]), key
+
+
 def test_autotune(ctx, tmp_path):
     p = W.random_small(90, S=3000, T=12, n_obs=7)
     ctx.set_path(406, p.path, p.ds)
