@@ -94,6 +94,26 @@ __device__ __forceinline__ float4 gld4(const float4* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void gst(float* p, float v) { *(__attribute__((address_space(1))) float*)p = v; }
+// GLB: through the global address space (the multi-lane forms, whose step has
+// one wave per SIMD or so and nothing to hide a needless wait), or through the
+// pointer as it is (the one-lane forms, whose register budget is the limit:
+// the global forms let the compiler hoist loads and lengthen live ranges)
+template <bool GLB>
+__device__ __forceinline__ float ldf(const float* p) {
+  if constexpr (GLB) return gld(p);
+  else return *p;
+}
+template <bool GLB>
+__device__ __forceinline__ void stf(float* p, float v) {
+  if constexpr (GLB) gst(p, v);
+  else *p = v;
+}
+
+// Per-lane choices inside the step are written as selects marked
+// unpredictable, so that the compiler keeps them as lane selects instead of
+// divergent branches (each of which costs exec-mask instructions and splits
+// the step into separately scheduled regions).
+__device__ __forceinline__ float sel(bool c, float a, float b) { return __builtin_unpredictable(c) ? a : b; }
 
 // Obstacle staged in LDS: centre relative to the tile origin, velocity; for
 // e = 2 the shape matrix Q = R' diag((mx+r)^-2, (my+r)^-2) R of eq. (16), for
@@ -110,6 +130,7 @@ struct RefPoint {
 // Reference zeta(psi): linear interpolation between waypoints, headings by the
 // wrapped difference, clamped to the ends.  f = phi0 + psi_rel/ds is the
 // fractional waypoint index relative to k0.
+template <bool GLB>
 __device__ __forceinline__ RefPoint reference(float f, int k0, int n_path, const float4* __restrict__ spath,
                                               int w0, int nw, const float4* __restrict__ gpath, float ox,
                                               float oy) {
@@ -125,18 +146,39 @@ __device__ __forceinline__ RefPoint reference(float f, int k0, int n_path, const
     t = 1.0f;
   }
   if (!(t >= 0.0f)) t = 0.0f;
-  // the window in LDS is read unconditionally (nw >= 2, so the clamped index
-  // is in range); a point outside it is fetched from HBM instead
   const int li = gi - w0;
-  const int lc = min(max(li, 0), nw - 2);
-  float4 A = spath[lc], B = spath[lc + 1];
-  if (!(li >= 0 && li + 1 < nw)) {
-    A = gld4(gpath + gi);
-    B = gld4(gpath + gi + 1);
-    A.x -= ox;
-    A.y -= oy;
-    B.x -= ox;
-    B.y -= oy;
+  float4 A, B;
+  if constexpr (GLB) {
+    // the window in LDS serves every lane unless one leaves it: then (a
+    // wave-uniform, rare case) each lane reads its point from LDS or HBM
+    // through a generic pointer
+    const int lc = min(max(li, 0), nw - 2);
+    const bool outside = !(li >= 0 && li + 1 < nw);
+    if (__any(outside)) {
+      const float4* pa = outside ? gpath + gi : spath + lc;
+      A = pa[0];
+      B = pa[1];
+      const float dx = outside ? ox : 0.0f, dy = outside ? oy : 0.0f;
+      A.x -= dx;
+      A.y -= dy;
+      B.x -= dx;
+      B.y -= dy;
+    } else {
+      A = spath[lc];
+      B = spath[lc + 1];
+    }
+  } else {
+    if (li >= 0 && li + 1 < nw) {
+      A = spath[li];
+      B = spath[li + 1];
+    } else {
+      A = gpath[gi];
+      B = gpath[gi + 1];
+      A.x -= ox;
+      A.y -= oy;
+      B.x -= ox;
+      B.y -= oy;
+    }
   }
   RefPoint r;
   r.x = A.x + t * (B.x - A.x);
@@ -185,7 +227,7 @@ struct RowTerms {
 __device__ __forceinline__ RowTerms row_terms(const ProjConst& K, float hhat, float Lf, float g0, float g1,
                                               float atil, float alpha) {
   const float ah = fabsf(hhat);
-  const float hh = (ah < K.h_eps) ? (hhat < 0.0f ? -K.h_eps : K.h_eps) : hhat;
+  const float hh = sel(ah < K.h_eps, sel(hhat < 0.0f, -K.h_eps, K.h_eps), hhat);
   const float b = -Lf - alpha * hh;
   const float abar = (K.W_a * atil + K.rho * (K.amid - alpha)) * K.inv_Ma;
   RowTerms R;
@@ -423,8 +465,8 @@ __device__ __forceinline__ StepTrig step_trig(int g, float a0, float a1, float a
     t.cr = group_bcast<2, 1>(c2);
   } else {
     // lane g of every quad: angle g mod 4
-    const int k = g & 3;
-    const float a = k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
+    const bool odd = (g & 1) != 0, high = (g & 2) != 0;
+    const float a = sel(high, sel(odd, a3, a2), sel(odd, a1, a0));
     float sa, ca;
     step_sincos(a, &sa, &ca);
     t.s1 = group_bcast<G, 0>(sa);
@@ -513,8 +555,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // state update; the other forms have waves enough to hide them and fewer
   // registers to spare.  Both orders compute the same values.
   constexpr bool kAhead = (G == 8);
-  RefPoint rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
-  float un_j = gld(unom + 0), un_w = gld(unom + 1), un_nu = gld(unom + 2);
+  constexpr bool kGlb = (G > 1);
+  RefPoint rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  float un_j = ldf<kGlb>(unom + 0), un_w = ldf<kGlb>(unom + 1), un_nu = ldf<kGlb>(unom + 2);
 
   // Precomputed normals are loaded PF = 2 steps ahead into a queue of two
   // slots: step tau reads slot tau % 2 and refills it with step tau + 2.  The
@@ -532,13 +575,13 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     if constexpr (PRE) {
       const float* __restrict__ base = d.noise + (size_t)tau * step_stride + s;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) nx_in[q][k] = gld(base + (size_t)k * S_pad);
+      for (int k = 0; k < 3; ++k) nx_in[q][k] = ldf<kGlb>(base + (size_t)k * S_pad);
 #pragma unroll
       for (int k = 0; k < NH; ++k)
-        nx_h[q][k] = gld(base + (size_t)min((uint32_t)(3 + hk0 + k), n_rows - 1) * S_pad);
+        nx_h[q][k] = ldf<kGlb>(base + (size_t)min((uint32_t)(3 + hk0 + k), n_rows - 1) * S_pad);
 #pragma unroll
       for (int j = 0; j < NSL; ++j)
-        nx_o[q][j] = gld(base + (size_t)min((uint32_t)(5 + g + G * j), n_rows - 1) * S_pad);
+        nx_o[q][j] = ldf<kGlb>(base + (size_t)min((uint32_t)(5 + g + G * j), n_rows - 1) * S_pad);
     }
   };
   if constexpr (PRE) {
@@ -579,25 +622,25 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       }
     }
     if constexpr (!kAhead) {
-      un_j = gld(unom + 3 * tau + 0);
-      un_w = gld(unom + 3 * tau + 1);
-      un_nu = gld(unom + 3 * tau + 2);
+      un_j = ldf<kGlb>(unom + 3 * tau + 0);
+      un_w = ldf<kGlb>(unom + 3 * tau + 1);
+      un_nu = ldf<kGlb>(unom + 3 * tau + 2);
     }
     float uj = un_j + P.sigma_j * e_in[0];
     float uw = un_w + P.sigma_w * e_in[1];
     const float unu = un_nu + P.sigma_nu * e_in[2];
     if constexpr (kAhead) {
       const uint32_t tn = min(tau + 1, d.T - 1);
-      un_j = gld(unom + 3 * tn + 0);
-      un_w = gld(unom + 3 * tn + 1);
-      un_nu = gld(unom + 3 * tn + 2);
+      un_j = ldf<kGlb>(unom + 3 * tn + 0);
+      un_w = ldf<kGlb>(unom + 3 * tn + 1);
+      un_nu = ldf<kGlb>(unom + 3 * tn + 2);
     }
     const float psi_next = psi + Ts * unu;
     RefPoint rf_next;
     if constexpr (kAhead) {
-      rf_next = reference(phi0 + psi_next * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      rf_next = reference<kGlb>(phi0 + psi_next * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     } else if (tau > 0) {
-      rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     }
     const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
     const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
@@ -641,7 +684,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           // lanes 0 and 1 hold the hitch rows; the others add exact zeros
           // (an accumulator is never -0, so x + 0 keeps its bits)
           RowTerms Hz = H[0];
-          if (!(hitch && vl < 2)) Hz.c = Hz.g0 = Hz.g1 = Hz.rr = 0.0f;
+          const bool own = hitch && vl < 2;
+          Hz.c = sel(own, Hz.c, 0.0f);
+          Hz.g0 = sel(own, Hz.g0, 0.0f);
+          Hz.g1 = sel(own, Hz.g1, 0.0f);
+          Hz.rr = sel(own, Hz.rr, 0.0f);
           acc_row(A, Hz);
         }
 #pragma unroll
@@ -658,7 +705,13 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
             // slot and contribute zeros, without a divergent branch
             const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
             RowTerms Rt = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
-            if (!(o < n_obs)) Rt.c = Rt.g0 = Rt.g1 = Rt.rr = Rt.Lf = Rt.ih = 0.0f;
+            const bool live = o < n_obs;
+            Rt.c = sel(live, Rt.c, 0.0f);
+            Rt.g0 = sel(live, Rt.g0, 0.0f);
+            Rt.g1 = sel(live, Rt.g1, 0.0f);
+            Rt.rr = sel(live, Rt.rr, 0.0f);
+            Rt.Lf = sel(live, Rt.Lf, 0.0f);
+            Rt.ih = sel(live, Rt.ih, 0.0f);
             O[j] = Rt;
             acc_row(A, O[j]);
           }
@@ -693,17 +746,17 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     J += (double)rc;
 
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
-    if (store) {
-      if (d.ustar_global) {
-        gst(ustar + (size_t)(3 * tau + 0) * S_pad + s, uj);
-        gst(ustar + (size_t)(3 * tau + 1) * S_pad + s, uw);
-        gst(ustar + (size_t)(3 * tau + 2) * S_pad + s, unu);
-      }
-      if (s_u) {
-        s_u[(3 * tau + 0) * lds_stride + t_local] = uj;
-        s_u[(3 * tau + 1) * lds_stride + t_local] = uw;
-        s_u[(3 * tau + 2) * lds_stride + t_local] = unu;
-      }
+    if (d.ustar_global && store) {
+      stf<kGlb>(ustar + (size_t)(3 * tau + 0) * S_pad + s, uj);
+      stf<kGlb>(ustar + (size_t)(3 * tau + 1) * S_pad + s, uw);
+      stf<kGlb>(ustar + (size_t)(3 * tau + 2) * S_pad + s, unu);
+    }
+    if (s_u) {
+      // every lane of the sample writes the same values to its column; the
+      // column of a sample past S is never weighted
+      s_u[(3 * tau + 0) * lds_stride + t_local] = uj;
+      s_u[(3 * tau + 1) * lds_stride + t_local] = uw;
+      s_u[(3 * tau + 2) * lds_stride + t_local] = unu;
     }
 
     // --- explicit Euler, eq. (6), plus psi_dot = nu ---
@@ -732,7 +785,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   } else {
     for (uint32_t tau = 0; tau < d.T; ++tau) step(tau, std::integral_constant<int, 0>{});
   }
-  if constexpr (!kAhead) rf = reference(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  if constexpr (!kAhead) rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
   if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
   J += (double)rN;
