@@ -1165,7 +1165,7 @@ __device__ __forceinline__ void group_sums(const float4* up, const float* sig, u
 
 // Group merge by the last tile of the group: m_g, unit scales, (Z_g, Z2_g)
 // and the group row sums from the units' partials.
-__device__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint32_t nu_g, float* s_sig,
+__device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint32_t nu_g, float* s_sig,
                             float4* s_up, float* s_red) {
   const uint32_t t = threadIdx.x, nt = blockDim.x, R = 3 * d.T;
   // this thread's first row: all the group's unit sums, loaded before the
@@ -1213,11 +1213,12 @@ __device__ void group_merge(const SolveDesc& d, uint32_t grp, uint32_t gu0, uint
 // Waves per SIMD the register allocation must leave room for.  Up to 16
 // obstacle slots every launch shape fits two waves (the one-lane forms with a
 // few spilled values, which still pays: at one wave per SIMD nothing hides the
-// step's latency); with 32 slots the one-lane forms would spill hundreds of
-// values, so they keep the whole register file.
-template <int NOB>
+// step's latency), and so do the four- and eight-lane forms with 32 slots (a
+// lane holds 8 or 4 obstacle rows); the one- and two-lane forms with 32 slots
+// would spill hundreds of values, so they keep the whole register file.
+template <int NOB, int G>
 constexpr int rollout_waves_per_simd() {
-  return NOB <= 16 ? 2 : 1;
+  return (NOB <= 16 || G >= 4) ? 2 : 1;
 }
 
 // W: the calling kernels' waves per SIMD.  Each class of callers gets its own
@@ -1282,7 +1283,7 @@ __device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile
 }
 
 template <int NOB, bool GUIDED, int G, bool PRE>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_simd<NOB>(), 8)))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(rollout_waves_per_simd<NOB, G>(), 8)))
 void k_rollout(const SolveDesc* __restrict__ descs,
                                                        const Tile* __restrict__ tiles, uint32_t n_tiles,
                                                        BatchCounters* __restrict__ ctr) {
@@ -1396,7 +1397,7 @@ void k_rollout(const SolveDesc* __restrict__ descs,
                                                  lds_stride, t_local, s_J);
     __syncthreads();
     if (fused)
-      tile_epilogue<rollout_waves_per_simd<NOB>()>(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig,
+      tile_epilogue<rollout_waves_per_simd<NOB, G>()>(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig,
                                                    s_up, s_red, s_trig, &s_flag);
   }
   if (ctr && threadIdx.x == 0) {
