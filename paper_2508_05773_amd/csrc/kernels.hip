@@ -60,18 +60,23 @@ __device__ __forceinline__ float unif23(uint32_t r) {
   return (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
 }
 
-// Box-Muller on the pairs (u0, u1) and (u2, u3)
+// Box-Muller on the pairs (u0, u1) and (u2, u3): radius sqrt(-2 ln u0),
+// angle 2 pi u1.  The uniforms lie in [2^-24, 1), so the hardware log2,
+// square root, sine and cosine need none of the library's range reduction or
+// special cases; the hardware sine and cosine take the angle in revolutions,
+// so 2 pi u1 is never rounded.  Over all 2^23 uniforms the radius is within
+// 4.9e-7 and the sine and cosine within 1.3e-7 of the exact values.
+constexpr float kLn2 = 0.693147182f;
+__device__ __forceinline__ float bm_radius(float u) {
+  return __builtin_amdgcn_sqrtf(-2.0f * kLn2 * __builtin_amdgcn_logf(u));
+}
 __device__ __forceinline__ void box_muller4(const uint32_t r[4], float* n) {
   const float u0 = unif23(r[0]), u1 = unif23(r[1]), u2 = unif23(r[2]), u3 = unif23(r[3]);
-  const float rad0 = sqrtf(-2.0f * logf(u0));
-  const float rad1 = sqrtf(-2.0f * logf(u2));
-  float s1, c1, s3, c3;
-  sincospif(2.0f * u1, &s1, &c1);
-  sincospif(2.0f * u3, &s3, &c3);
-  n[0] = rad0 * c1;
-  n[1] = rad0 * s1;
-  n[2] = rad1 * c3;
-  n[3] = rad1 * s3;
+  const float rad0 = bm_radius(u0), rad1 = bm_radius(u2);
+  n[0] = rad0 * __builtin_amdgcn_cosf(u1);
+  n[1] = rad0 * __builtin_amdgcn_sinf(u1);
+  n[2] = rad1 * __builtin_amdgcn_cosf(u3);
+  n[3] = rad1 * __builtin_amdgcn_sinf(u3);
 }
 
 constexpr float kTwoPi = 6.283185307179586f;

@@ -2,7 +2,9 @@
 
 Bars (FP32 GPU vs FP64 oracle):
   - Philox u32 blocks bit-exact;
-  - normals within 1e-6 (relative, absolute below 1);
+  - normals within 1.5e-6 absolute (the FP32 Box-Muller from the same bits:
+    radius within 4.9e-7 and sine/cosine within 1.3e-7 over all 2^23
+    uniforms, radius at most 5.8, plus half an ulp of the product);
   - per-sample rollout cost within relative 1e-4 on every sample;
   - new nominal sequence within 1e-4 of each input's range
     (jerk 4 m/s^3, steer rate 1.8 rad/s, progress rate nu_bar).
@@ -73,6 +75,10 @@ def test_philox_bit_exact(ctx):
             assert list(got[i]) == O.philox(ctr[i], key), (i, key)
 
 
+# |d n| <= |d rad| + rad_max |d trig| + ulp(rad_max) / 2 = 4.9e-7 + 5.8 * 1.3e-7 + 2.4e-7
+NORMAL_ATOL = 1.5e-6
+
+
 def test_normals_match_oracle(ctx):
     from oracle import oracle as O
     rng = np.random.default_rng(8)
@@ -81,8 +87,8 @@ def test_normals_match_oracle(ctx):
         st = rng.integers(0, 70000, size=(512, 2)).astype(np.uint32)
         got = B.brmppi_debug_normals(ctx.h, seed, inst, st, K)
         want = np.array([O.normals(seed, inst, int(s), int(t), K) for s, t in st])
-        err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
-        assert err.max() < 1e-6, err.max()
+        err = np.abs(got - want)
+        assert err.max() <= NORMAL_ATOL, err.max()
 
 
 def test_c1_full(ctx):
