@@ -99,6 +99,39 @@ __device__ __forceinline__ float4 gld4(const float4* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void gst(float* p, float v) { *(__attribute__((address_space(1))) float*)p = v; }
+// LDS reads and writes through local-address-space pointers.  The reduction
+// code below also runs in functions that are not inlined into the kernel,
+// where a pointer argument is generic: a generic access to LDS compiles to a
+// flat access, which is slower and counts against both wait counters.  Every
+// pointer passed to these helpers points into LDS.
+typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) gvec4 lds_vec4;
+__device__ __forceinline__ float lds(const float* p) { return *(const lds_float*)p; }
+__device__ __forceinline__ double lds(const double* p) { return *(const lds_double*)p; }
+__device__ __forceinline__ float4 lds(const float4* p) {
+  const gvec4 v = *(const lds_vec4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_put(float* p, float v) { *(lds_float*)p = v; }
+__device__ __forceinline__ void lds_put(double* p, double v) { *(lds_double*)p = v; }
+__device__ __forceinline__ void lds_put(float4* p, float4 v) {
+  gvec4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *(lds_vec4*)p = w;
+}
+__device__ __forceinline__ void gst4(float4* p, float4 v) {
+  gvec4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *(__attribute__((address_space(1))) gvec4*)p = w;
+}
+
 // GLB: through the global address space (the multi-lane forms, whose step has
 // one wave per SIMD or so and nothing to hide a needless wait), or through the
 // pointer as it is (the one-lane forms, whose register budget is the limit:
@@ -900,13 +933,13 @@ constexpr int kPlantLds = 17;
 __device__ __forceinline__ void plant_prep(const SolveDesc& d, double* s_plant) {
   const uint32_t t = threadIdx.x;
   const double* x = d.plant_x;
-  if (t < 8) s_plant[6 + t] = x[t];
+  if (t < 8) lds_put(s_plant + 6 + t, x[t]);
   if (t < 3) {
     const double ang = t == 0 ? x[4] : (t == 1 ? x[6] : x[4] - x[5]);
     double sn, cs;
     sincos(ang, &sn, &cs);
-    s_plant[2 * t] = sn;
-    s_plant[2 * t + 1] = cs;
+    lds_put(s_plant + 2 * t, sn);
+    lds_put(s_plant + 2 * t + 1, cs);
   }
 }
 // Hitch-angle stabiliser (Sec. IV-D, eq. (19)) in FP64: (j, w) <- argmin of
@@ -984,9 +1017,9 @@ __device__ bool hitch_qp(const brmppi_params& P, const double x[8], const double
 __device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s_plant) {
   const brmppi_params& P = d.prm;
   double x[8];
-  for (int k = 0; k < 8; ++k) x[k] = s_plant[6 + k];
-  double j = s_plant[14], w = s_plant[15];
-  const double nu = s_plant[16];
+  for (int k = 0; k < 8; ++k) x[k] = lds(s_plant + 6 + k);
+  double j = lds(s_plant + 14), w = lds(s_plant + 15);
+  const double nu = lds(s_plant + 16);
   const bool stabilised = (d.flags & BRMPPI_HITCH_QP) && hitch_qp(P, x, s_plant, j, w);
   if (!stabilised) {   // hard input bounds on the applied input
     j = fmin(fmax(j, (double)P.j_lo), (double)P.j_hi);
@@ -994,9 +1027,9 @@ __device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s
   }
   const double Ts = P.Ts, l1 = P.l1, l2 = P.l2, lh = P.lh;
   const double v = x[2], a = x[3];
-  const double s1 = s_plant[0], c1 = s_plant[1];
-  const double tan_dl = s_plant[2] / s_plant[3];
-  const double s12 = s_plant[4], c12 = s_plant[5];
+  const double s1 = lds(s_plant + 0), c1 = lds(s_plant + 1);
+  const double tan_dl = lds(s_plant + 2) / lds(s_plant + 3);
+  const double s12 = lds(s_plant + 4), c12 = lds(s_plant + 5);
   double xn[8];
   xn[0] = x[0] + Ts * v * c1;
   xn[1] = x[1] + Ts * v * s1;
@@ -1014,10 +1047,10 @@ __device__ __forceinline__ void plant_finish(const SolveDesc& d, const double* s
 __device__ __forceinline__ float block_min(float v, float* s_red) {
   v = wave_min(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 0) lds_put(s_red + (threadIdx.x >> 6), v);
   __syncthreads();
-  float r = s_red[0];
-  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = fminf(r, s_red[w]);
+  float r = lds(s_red);
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = fminf(r, lds(s_red + w));
   return r;
 }
 // two sums with one pair of barriers (s_red: 2 x 4 floats), each in the same
@@ -1027,14 +1060,14 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float* s_red) {
   b = wave_sum(b);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
-    s_red[threadIdx.x >> 6] = a;
-    s_red[4 + (threadIdx.x >> 6)] = b;
+    lds_put(s_red + (threadIdx.x >> 6), a);
+    lds_put(s_red + 4 + (threadIdx.x >> 6), b);
   }
   __syncthreads();
-  float ra = s_red[0], rb = s_red[4];
+  float ra = lds(s_red), rb = lds(s_red + 4);
   for (uint32_t w = 1; w < blockDim.x / 64; ++w) {
-    ra += s_red[w];
-    rb += s_red[4 + w];
+    ra += lds(s_red + w);
+    rb += lds(s_red + 4 + w);
   }
   a = ra;
   b = rb;
@@ -1057,19 +1090,19 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
   const uint32_t r0 = threadIdx.x;
   float pre[kPre];
 #pragma unroll
-  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? d.rpart[(size_t)k * R + r0] : 0.0f;
+  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? gld(d.rpart + (size_t)k * R + r0) : 0.0f;
   // this thread's first group partial is loaded once, for the minimum and the sums
-  const float4 w_first = threadIdx.x < nW ? d.wpart[threadIdx.x] : make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
+  const float4 w_first = threadIdx.x < nW ? gld4(d.wpart + threadIdx.x) : make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
   float mloc = w_first.x;
   for (uint32_t c = threadIdx.x + nt; c < nW; c += nt) {
-    mloc = fminf(mloc, d.wpart[c].x);
+    mloc = fminf(mloc, gld4(d.wpart + c).x);
   }
   const float m = block_min(mloc, s_red);
   float zl = 0.0f, z2l = 0.0f;
   for (uint32_t c = threadIdx.x; c < nW; c += nt) {
-    const float4 w = c == threadIdx.x ? w_first : d.wpart[c];
+    const float4 w = c == threadIdx.x ? w_first : gld4(d.wpart + c);
     const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
-    s_scale[c] = sc;
+    lds_put(s_scale + c, sc);
     zl += sc * w.y;
     z2l += sc * sc * w.z;
   }
@@ -1086,30 +1119,30 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
         const bool use_pre = (c == 0) && (r == r0);
         float v[kPre];
 #pragma unroll
-        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : col[(size_t)(c + k) * R];
+        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : gld(col + (size_t)(c + k) * R);
 #pragma unroll
-        for (int k = 0; k < kPre; ++k) acc += s_scale[c + k] * v[k];
+        for (int k = 0; k < kPre; ++k) acc += lds(s_scale + c + k) * v[k];
       }
 #pragma unroll
       for (int k = 0; k < kPre; ++k) {
         if (c + k < nW) {
-          const float vk = (c == 0 && r == r0) ? pre[k] : col[(size_t)(c + k) * R];
-          acc += s_scale[c + k] * vk;
+          const float vk = (c == 0 && r == r0) ? pre[k] : gld(col + (size_t)(c + k) * R);
+          acc += lds(s_scale + c + k) * vk;
         }
       }
       const float U = acc * iZ;
-      d.u_new[r] = U;
-      if (plant && r < 3) s_plant[14 + r] = (double)U;
+      gst(d.u_new + r, U);
+      if (plant && r < 3) lds_put(s_plant + 14 + r, (double)U);
       // receding-horizon shift: U_nom <- [U[1:], U[T-1]]
-      if (r >= 3) d.u_nom_out[r - 3] = U;
-      if (r + 3 >= R) d.u_nom_out[r] = U;
+      if (r >= 3) gst(d.u_nom_out + r - 3, U);
+      if (r + 3 >= R) gst(d.u_nom_out + r, U);
     }
   } else {
     // every cost non-finite: return the nominal sequence, keep the warm start
     for (uint32_t r = threadIdx.x; r < R; r += nt) {
-      const float U = d.u_nom_in[r];
-      d.u_new[r] = U;
-      if (plant && r < 3) s_plant[14 + r] = (double)U;
+      const float U = gld(d.u_nom_in + r);
+      gst(d.u_new + r, U);
+      if (plant && r < 3) lds_put(s_plant + 14 + r, (double)U);
     }
   }
   if (threadIdx.x == 0) {
@@ -1140,7 +1173,7 @@ __device__ __forceinline__ void unit_sums(const float* gam, float& z, float& z2)
   z2 = 0.0f;
 #pragma unroll
   for (int i = 0; i < kUnit; ++i) {
-    const float gm = gam[i];
+    const float gm = lds(gam + i);
     z = z + gm;
     z2 = fmaf(gm, gm, z2);
   }
@@ -1155,15 +1188,27 @@ __device__ __forceinline__ float merge_scale(float m, float mg, float inv_lambda
   return (mg < INFINITY && m < INFINITY) ? expf(-(m - mg) * inv_lambda) : 0.0f;
 }
 // group (Z, Z2) from its units' (m_u, Z_u, Z2_u) and scales, in unit order
+// (entries are read kChunk at a time, in bounds, before any of them is used,
+// so that the reads are not serialised behind the per-unit condition)
+constexpr int kChunk = 8;
 __device__ __forceinline__ void group_sums(const float4* up, const float* sig, uint32_t nu, float& z, float& z2) {
   z = 0.0f;
   z2 = 0.0f;
 #pragma unroll
-  for (int u = 0; u < kGroupUnits; ++u) {
-    if ((uint32_t)u < nu) {
-      const float sc = sig[u];
-      z = fmaf(sc, up[u].y, z);
-      z2 = fmaf(sc * sc, up[u].z, z2);
+  for (int c = 0; c < kGroupUnits; c += kChunk) {
+    float sc[kChunk];
+    float4 q[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      q[k] = lds(up + c + k);
+      sc[k] = lds(sig + c + k);
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      if ((uint32_t)(c + k) < nu) {
+        z = fmaf(sc[k], q[k].y, z);
+        z2 = fmaf(sc[k] * sc[k], q[k].z, z2);
+      }
     }
   }
 }
@@ -1175,18 +1220,20 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
   const uint32_t t = threadIdx.x, nt = blockDim.x, R = 3 * d.T;
   // this thread's first row: all the group's unit sums, loaded before the
   // minimum (they do not depend on it)
+  // (units past nu_g read the group's last unit, in range; only terms of units
+  // below nu_g are ever used)
   float v0[kGroupUnits];
   {
     const float* __restrict__ col = d.urow + (size_t)gu0 * R + (t < R ? t : 0);
 #pragma unroll
-    for (int u = 0; u < kGroupUnits; ++u) v0[u] = (t < R && (uint32_t)u < nu_g) ? col[(size_t)u * R] : 0.0f;
+    for (int u = 0; u < kGroupUnits; ++u) v0[u] = gld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
   }
   float4 up = make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
-  if (t < nu_g) up = d.upart[gu0 + t];
+  if (t < nu_g) up = gld4(d.upart + gu0 + t);
   const float mg = block_min(up.x, s_red);
   if (t < nu_g) {
-    s_up[t] = up;
-    s_sig[t] = merge_scale(up.x, mg, d.inv_lambda);
+    lds_put(s_up + t, up);
+    lds_put(s_sig + t, merge_scale(up.x, mg, d.inv_lambda));
   }
   __syncthreads();
   // the group's (Z, Z2), on the first thread of a wave without a row when there
@@ -1195,20 +1242,31 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
   if (t == tz) {
     float z, z2;
     group_sums(s_up, s_sig, nu_g, z, z2);
-    d.wpart[grp] = make_float4(mg, z, z2, 0.0f);
+    gst4(d.wpart + grp, make_float4(mg, z, z2, 0.0f));
   }
-  for (uint32_t r = t; r < R; r += nt) {
+  // one row: its unit sums in v, the scales read kChunk at a time (in bounds,
+  // before any of them is used)
+  auto row_sum = [&](uint32_t r, const float* v) __attribute__((always_inline)) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kGroupUnits; c += kChunk) {
+      float sg[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) sg[k] = lds(s_sig + c + k);
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k)
+        if ((uint32_t)(c + k) < nu_g) acc = unit_row_term(acc, sg[k], v[c + k]);
+    }
+    gst(d.rpart + (size_t)grp * R + r, acc);
+  };
+  if (t < R) row_sum(t, v0);
+  for (uint32_t r = t + nt; r < R; r += nt) {
     // all the group's unit sums of this row are loaded at once: one latency
     const float* __restrict__ col = d.urow + (size_t)gu0 * R + r;
     float v[kGroupUnits];
 #pragma unroll
-    for (int u = 0; u < kGroupUnits; ++u)
-      v[u] = (r == t) ? v0[u] : (((uint32_t)u < nu_g) ? col[(size_t)u * R] : 0.0f);
-    float acc = 0.0f;
-#pragma unroll
-    for (int u = 0; u < kGroupUnits; ++u)
-      if ((uint32_t)u < nu_g) acc = unit_row_term(acc, s_sig[u], v[u]);
-    d.rpart[(size_t)grp * R + r] = acc;
+    for (int u = 0; u < kGroupUnits; ++u) v[u] = gld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
+    row_sum(r, v);
   }
 }
 
@@ -1238,18 +1296,18 @@ __device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile
   const uint32_t nu_tile = min(k_units, d.n_units - u0);
   // unit minimum (exact in any order) and weights; a unit is half a wave
   if (t < per_tile) {
-    const float j = s_J[t];
+    const float j = lds(s_J + t);
     float m = j;
 #pragma unroll
     for (int o = kUnit / 2; o >= 1; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
-    s_gam[t] = unit_weight(j, m, d.inv_lambda);
-    if ((t & (kUnit - 1)) == 0) s_mu[t / kUnit] = m;
+    lds_put(s_gam + t, unit_weight(j, m, d.inv_lambda));
+    if ((t & (kUnit - 1)) == 0) lds_put(s_mu + t / kUnit, m);
   }
   __syncthreads();
   if (t < nu_tile) {
     float z, z2;
     unit_sums(s_gam + kUnit * t, z, z2);
-    d.upart[u0 + t] = make_float4(s_mu[t], z, z2, 0.0f);
+    gst4(d.upart + u0 + t, make_float4(lds(s_mu + t), z, z2, 0.0f));
   }
   for (uint32_t it = t; it < nu_tile * R; it += nt) {
     const uint32_t j = it / R, r = it - j * R;
@@ -1257,8 +1315,17 @@ __device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile
     const float* u = s_u + r * lds_stride + kUnit * j;
     float acc = 0.0f;
 #pragma unroll
-    for (int i = 0; i < kUnit; ++i) acc = unit_row_term(acc, gam[i], u[i]);
-    d.urow[(size_t)(u0 + j) * R + r] = acc;
+    for (int c = 0; c < kUnit; c += kChunk) {
+      float g8[kChunk], u8[kChunk];
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) {
+        g8[k] = lds(gam + c + k);
+        u8[k] = lds(u + c + k);
+      }
+#pragma unroll
+      for (int k = 0; k < kChunk; ++k) acc = unit_row_term(acc, g8[k], u8[k]);
+    }
+    gst(d.urow + (size_t)(u0 + j) * R + r, acc);
   }
   // publish the tile's units; the last tile of the group merges it
   const uint32_t grp = u0 / kGroupUnits, gu0 = grp * kGroupUnits;
