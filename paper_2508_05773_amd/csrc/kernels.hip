@@ -1284,10 +1284,10 @@ constexpr int rollout_waves_per_simd() {
   return (NOB <= 16 || G >= 4) ? 2 : 1;
 }
 
-// W: the calling kernels' waves per SIMD.  Each class of callers gets its own
-// copy, so that the copy is compiled within the same register budget.
-template <int W>
-__device__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile, float* s_u, uint32_t lds_stride,
+// Inlined into the kernel: as a function call, every lane saved and restored
+// its callee-saved registers around it (tens of bytes of scratch per lane,
+// written back to HBM by the publish fences).
+__device__ __forceinline__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile, float* s_u, uint32_t lds_stride,
                               const float* s_J, float* s_gam, float* s_mu, float* s_sig, float4* s_up,
                               float* s_red, double* s_trig, uint32_t* s_flag) {
   const uint32_t t = threadIdx.x, nt = blockDim.x, R = 3 * d.T;
@@ -1469,8 +1469,7 @@ void k_rollout(const SolveDesc* __restrict__ descs,
                                                  lds_stride, t_local, s_J);
     __syncthreads();
     if (fused)
-      tile_epilogue<rollout_waves_per_simd<NOB, G>()>(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig,
-                                                   s_up, s_red, s_trig, &s_flag);
+      tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);
   }
   if (ctr && threadIdx.x == 0) {
     fence_release();
@@ -1556,7 +1555,9 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
 #pragma unroll
       for (int j = 0; j < kRedRows; ++j) {
         const uint32_t rr = p + (uint32_t)j;
-        q[j] = (sv && rr < nrow) ? *reinterpret_cast<const float4*>(colp + (size_t)(r0 + rr) * d.S_pad)
+        // global-space loads: a flat load would also count against the LDS wait
+        // counter, and the tile's LDS reads would wait for the next rows' loads
+        q[j] = (sv && rr < nrow) ? gld4(reinterpret_cast<const float4*>(colp + (size_t)(r0 + rr) * d.S_pad))
                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       }
     };
@@ -1565,7 +1566,7 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     // costs and unit weights
     float jv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     if (sv) {
-      const float4 c = *reinterpret_cast<const float4*>(d.J + s4);
+      const float4 c = gld4(reinterpret_cast<const float4*>(d.J + s4));
       jv[0] = c.x;
       jv[1] = c.y;
       jv[2] = c.z;
