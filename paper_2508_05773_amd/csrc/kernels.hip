@@ -761,7 +761,12 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       const double y0 = (double)(P.W_j * uj + pj0) + S8.y0;
       const double y1 = (double)(P.W_w * uw + pw0) + S8.y1;
       const double det = N00 * N11 - N01 * N01;
-      const double idet = 1.0 / det;
+      // det > 0 (N is the diagonal W + rho I plus positive semidefinite rank-one
+      // terms): the hardware reciprocal and two Newton steps give 1/det to the
+      // last bits, in 5 instructions instead of the IEEE division's 12
+      double idet = __builtin_amdgcn_rcp(det);
+      idet = fma(fma(-det, idet, 1.0), idet, idet);
+      idet = fma(fma(-det, idet, 1.0), idet, idet);
       uj = (float)((N11 * y0 - N01 * y1) * idet);
       uw = (float)((N00 * y1 - N01 * y0) * idet);
       // next barrier rates: alpha + u*alpha = -(Lf + g u*)/hh (eq. (9) holds exactly)
