@@ -160,6 +160,34 @@ def test_edge_shapes(ctx, S, T, n_obs):
     compare(prob, g, o, f"edge S={S} T={T} n_obs={n_obs}")
 
 
+def test_reference_outside_lds_window(ctx):
+    """c1 on a path of 0.005 m spacing with a nominal progress rate of nu_bar:
+    the 1024 waypoints staged in LDS cover about 5 m ahead of the start and the
+    rollouts progress about 6 m, so the last steps read their reference points
+    from HBM.  One, two and eight lanes per sample (the forms read the path in
+    different ways) against the oracle, and against each other bitwise."""
+    from oracle import oracle as O
+    p = W.config1()
+    path, _ = W.path_c1(ds=0.005)
+    u_nom = p.u_nom.copy()
+    u_nom[:, 2] = p.params["nu_bar"]
+    p = p.copy(path=path, ds=0.005, S=1500, u_nom=u_nom)
+    assert p.T * p.params["Ts"] * p.params["nu_bar"] > 1024 * 0.005
+    o = O.solve(p, nthreads=NTHREADS)
+    ref = None
+    for block, variant in ((64, 0), (128, 2), (256, 4)):
+        B.brmppi_set_launch(ctx.h, block, variant)
+        try:
+            g = run_gpu(ctx, p, controller=26)
+        finally:
+            B.brmppi_set_launch(ctx.h, 0, 0)
+        compare(p, g, o, f"fine path block={block} variant={variant}")
+        if ref is None:
+            ref = g
+        else:
+            assert np.array_equal(g["J"], ref["J"]) and np.array_equal(g["U_new"], ref["U_new"])
+
+
 def test_nonfinite_returns_nominal(ctx):
     prob = W.random_small(40, S=300, T=6, n_obs=2)
     bad = prob.copy()
