@@ -117,8 +117,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs the control update on one MI355X; this build has no multi-GPU path "
-              "(one GPU per box). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures the control update on one MI355X; runs on several GPUs are not "
+              "supported. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
