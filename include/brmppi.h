@@ -249,7 +249,8 @@ int brmppi_autotune(brmppi_ctx* ctx);
  * the kernel; 1 = one lane, noise from the parallel kernel; 2 / 3 / 4 = two /
  * four / eight lanes per sample, noise from the parallel kernel (batched
  * launches always use variant 0; an instance without guidance runs variant
- * 0 or 1).  block 0 restores the tuned/default choice.  EINVAL for a block
+ * 0 or 1; a plain solve whose normals would take more than 2 GiB or half the
+ * arena runs variant 0).  block 0 restores the tuned/default choice.  EINVAL for a block
  * outside 64..256 or not a multiple of 64, or a variant above 4. */
 int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant);
 /* Kernel timings accumulated under BRMPPI_CTX_PROFILE (every kernel of the
