@@ -207,14 +207,16 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0,
 }
 
 // rows of one reduce work item for a launch over these instances: the most
-// rows (fewest barriers and publishes per byte) that still give every CU
-// several items
+// rows (fewest barriers and publishes per byte) that still give every CU an
+// item.  Asking for several items per CU (smaller items) was measured slower:
+// the per-item weights, barriers and publish cost more than the finer balance
+// gains.
 uint32_t reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu) {
   for (uint32_t r = kMaxRowsPerItem; r > kRowsPerPass; r /= 2) {
     size_t items = 0;
     for (uint32_t i = 0; i < n; ++i)
       items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * ((3 * ps[i]->T + r - 1) / r);
-    if (items >= 6 * (size_t)n_cu) return r;
+    if (items >= (size_t)n_cu) return r;
   }
   return kRowsPerPass;
 }
