@@ -99,11 +99,11 @@ __device__ __forceinline__ float4 gld4(const float4* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void gst(float* p, float v) { *(__attribute__((address_space(1))) float*)p = v; }
-// LDS reads and writes through local-address-space pointers.  The reduction
-// code below also runs in functions that are not inlined into the kernel,
-// where a pointer argument is generic: a generic access to LDS compiles to a
-// flat access, which is slower and counts against both wait counters.  Every
-// pointer passed to these helpers points into LDS.
+// LDS reads and writes through local-address-space pointers (and gst4, a
+// 16-byte global store).  The instance merge is a function of its own, not
+// inlined into the kernel, where a pointer argument is generic: a generic
+// access to LDS compiles to a flat access, which is slower and counts against
+// both wait counters.  Every pointer passed to the LDS helpers points into LDS.
 typedef __attribute__((address_space(3))) float lds_float;
 typedef __attribute__((address_space(3))) double lds_double;
 typedef __attribute__((address_space(3))) gvec4 lds_vec4;
