@@ -842,29 +842,37 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 
 
 // ---------------------------------------------------------------------------
-// Noise: every (sample, step) in parallel, all its Philox blocks in one thread
-// (independent chains the scheduler interleaves) -> [tau][k][S_pad]
+// Noise: every (four consecutive samples, step) in parallel, all their Philox
+// blocks in one thread (independent chains the scheduler interleaves) ->
+// [tau][k][S_pad], one 16-byte store per lane and row
 // ---------------------------------------------------------------------------
 constexpr int kMaxPhiloxBlocks = (5 + BRMPPI_MAX_OBS + 3) / 4;
 
 __global__ __launch_bounds__(256) void k_noise(const char* __restrict__ descs, uint32_t stride, uint32_t nb) {
-  // blockIdx.z = update u of a run of consecutive descriptors
+  // blockIdx.z = update u of a run of consecutive descriptors; a thread draws
+  // four consecutive samples at step blockIdx.y and stores each row of normals
+  // with one 16-byte store (samples from S up to S_pad get the normals of
+  // their own indices, which nothing reads)
   const SolveDesc& d = *reinterpret_cast<const SolveDesc*>(descs + (size_t)blockIdx.z * stride);
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
   const uint32_t tau = blockIdx.y;
-  if (s >= d.S) return;
-  float* __restrict__ out = d.noise + (size_t)tau * d.n_normals * d.S_pad + s;
+  if (s0 >= d.S_pad) return;
+  float* __restrict__ out = d.noise + (size_t)tau * d.n_normals * d.S_pad + s0;
 #pragma unroll
   for (int b = 0; b < kMaxPhiloxBlocks; ++b) {
     if ((uint32_t)b < nb) {
-      uint32_t r[4];
-      float e[4];
-      philox4x32_10(s, tau, (uint32_t)b, d.instance, d.seed_lo, d.seed_hi, r);
-      box_muller4(r, e);
+      float e[4][4];
+#pragma unroll
+      for (uint32_t i = 0; i < 4; ++i) {
+        uint32_t r[4];
+        philox4x32_10(s0 + i, tau, (uint32_t)b, d.instance, d.seed_lo, d.seed_hi, r);
+        box_muller4(r, e[i]);
+      }
 #pragma unroll
       for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t kk = 4 * (uint32_t)b + k;
-        if (kk < d.n_normals) out[(size_t)kk * d.S_pad] = e[k];
+        if (kk < d.n_normals)
+          gst4(reinterpret_cast<float4*>(out + (size_t)kk * d.S_pad), make_float4(e[0][k], e[1][k], e[2][k], e[3][k]));
       }
     }
   }
@@ -1789,7 +1797,8 @@ hipError_t launch_noise(const SolveDesc* first, size_t stride, uint32_t count, u
                         uint32_t n_normals, hipStream_t stream) {
   const uint32_t nb = (n_normals + 3) / 4;
   if (count == 0 || nb == 0 || nb > (uint32_t)kMaxPhiloxBlocks) return count == 0 || nb == 0 ? hipSuccess : hipErrorInvalidValue;
-  const dim3 grid((S + 255) / 256, T, count);
+  const uint32_t S_pad = (S + 255u) & ~255u;   // the noise buffer's row length
+  const dim3 grid((S_pad + 1023) / 1024, T, count);
   hipLaunchKernelGGL(k_noise, grid, dim3(256), 0, stream, reinterpret_cast<const char*>(first), (uint32_t)stride, nb);
   return hipGetLastError();
 }
