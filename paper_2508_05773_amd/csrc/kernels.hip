@@ -547,7 +547,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   constexpr int NV = 8 / G;                            // virtual lanes of this lane
   constexpr int NH = (G == 1) ? 2 : 1;                 // hitch rows computed by this lane
   constexpr int NBMAX = GUIDED ? (5 + NOB + 3) / 4 : 1;  // Philox blocks (fused noise)
-  const brmppi_params& P = d.prm;
+  // a copy: the compiler keeps the parameters in registers instead of
+  // re-reading the descriptor (a scalar load and a wait) inside the step
+  const brmppi_params P = d.prm;
   const float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
   const float inv_l1 = 1.0f / P.l1, inv_l2 = 1.0f / P.l2, ch = P.lh / P.l1;
   const int n_obs = (int)d.n_obs;
