@@ -550,6 +550,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // a copy: the compiler keeps the parameters in registers instead of
   // re-reading the descriptor (a scalar load and a wait) inside the step
   const brmppi_params P = d.prm;
+  const float t0 = d.t0, inv_ds = d.inv_ds;
   const float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
   const float inv_l1 = 1.0f / P.l1, inv_l2 = 1.0f / P.l2, ch = P.lh / P.l1;
   const int n_obs = (int)d.n_obs;
@@ -596,7 +597,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // registers to spare.  Both orders compute the same values.
   constexpr bool kAhead = (G == 8);
   constexpr bool kGlb = (G > 1);
-  RefPoint rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  RefPoint rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float un_j = ldf<kGlb>(unom + 0), un_w = ldf<kGlb>(unom + 1), un_nu = ldf<kGlb>(unom + 2);
 
   // Precomputed normals are loaded PF = 2 steps ahead into a queue of two
@@ -678,9 +679,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float psi_next = psi + Ts * unu;
     RefPoint rf_next;
     if constexpr (kAhead) {
-      rf_next = reference<kGlb>(phi0 + psi_next * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      rf_next = reference<kGlb>(phi0 + psi_next * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     } else if (tau > 0) {
-      rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     }
     const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
     const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
@@ -691,7 +692,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 
     if (GUIDED && guided) {
       const float sec2 = 1.0f + tn * tn;
-      const float t = d.t0 + (float)tau * Ts;
+      const float t = t0 + (float)tau * Ts;
 
       // hitch rows, eq. (18) split into h_s = dth_max - kappa v + s (th1 - th2),
       // first-order expansion hhat = h + Ts hd
@@ -787,7 +788,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float prog = P.nu_bar - unu;
     float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
                P.R_w * uw * uw + P.mu * prog * prog;
-    if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)tau * Ts);
+    if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)tau * Ts);
     J += (double)rc;
 
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
@@ -830,9 +831,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   } else {
     for (uint32_t tau = 0; tau < d.T; ++tau) step(tau, std::integral_constant<int, 0>{});
   }
-  if constexpr (!kAhead) rf = reference<kGlb>(phi0 + psi * d.inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  if constexpr (!kAhead) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
-  if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, d.t0 + (float)d.T * Ts);
+  if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)d.T * Ts);
   J += (double)rN;
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
