@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-solves", type=int, default=300)
     ap.add_argument("--served-seconds", type=float, default=0.3, help="simulated seconds of the served leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-extras", action="store_true", help="only the timed closed loop")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
@@ -165,15 +165,23 @@ def main():
         if args.warmup > 0:
             B.brmppi_closed_loop(c.h, pb, args.warmup, want_x=False, want_u=False)
         B.brmppi_profile_reset(c.h)
+        info0 = B.brmppi_get_info(c.h)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.brmppi_closed_loop(c.h, pb, args.steps, want_x=False, want_u=False)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, B.brmppi_get_state(c.h, 0)
+        el = time.perf_counter() - t0
+        info1 = B.brmppi_get_info(c.h)
+        # buffers the library had to re-allocate inside the timed call (the loop's
+        # scratch and staging do not depend on its length: this is 0)
+        grows = sum(info1[k] - info0[k] for k in ("scratch_grows", "pinned_grows"))
+        return el, B.brmppi_get_state(c.h, 0), grows
 
-    wall, x_end = timed_loop(ctx2)
+    wall, x_end, grows = timed_loop(ctx2)
+    if grows:
+        note(f"warning: {grows} buffer re-allocations inside the timed loop")
     value = S * T * args.steps / wall
-    wall_prof, _ = timed_loop(ctx)
+    wall_prof, _, _ = timed_loop(ctx)
     prof = B.brmppi_profile_read(h)
     roll_ms = prof["rollout"]["ms"] / max(prof["rollout"]["count"], 1)
     # the closed loop draws the normals of several updates per noise launch
@@ -197,9 +205,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "reverse parking closed loop: S=8192, T=50, Ts=0.05 s, 8 parked-vehicle "
-                               "ellipses, 200 receding-horizon updates, device-resident",
+        "config": {"workload": f"reverse parking closed loop: S=8192, T=50, Ts=0.05 s, 8 parked-vehicle "
+                               f"ellipses, {args.steps} receding-horizon updates timed after {args.warmup} "
+                               f"untimed ones, device-resident",
                    "S": S, "T": T, "n_obs": n_obs, "updates": args.steps},
+        "buffer_regrowths_in_timed_loop": grows,
         "solves_per_s": args.steps / wall,
         "ms_per_step_with_launch_events": wall_prof * 1e3 / args.steps,
         "final_state_finite": bool(np.all(np.isfinite(x_end))),
@@ -447,28 +457,65 @@ def served_leg(args, B, W, ctx):
     }
 
 
+def host_cpu():
+    """CPU model and thread counts of the host the oracle runs on"""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    # the box's CPU share: OMP_NUM_THREADS when set (16 on the GPU host), else
+    # every core this process may run on
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or avail
+    return {"model": model, "nproc": os.cpu_count(), "affinity_cpus": avail, "threads": min(share, avail)}
+
+
 def cpu_baseline(W, prob, seconds):
-    """The FP64 oracle on the host cores, on a bounded sample of the same update."""
+    """The FP64 oracle as it stands on the host cores: one c2 update (all
+    S = 8192 samples) on every host thread of the share and on one thread, the
+    c1 update likewise, and the 32-obstacle large update on a 512-sample
+    subset.  value = the c2 update on all threads."""
     from oracle import oracle as O
 
-    try:
-        cpus = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cpus = os.cpu_count() or 1
-    threads = max(1, min(16, cpus))
-    sub = prob.copy(S=1024)
-    O.solve(sub.copy(S=64), nthreads=threads)          # build + warm
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.solve(sub.copy(seed=sub.seed + reps), nthreads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    v = sub.S * sub.T * reps / el
+    cpu = host_cpu()
+    threads = cpu["threads"]
+    O.solve(W.config1().copy(S=64), nthreads=threads)          # build + warm
+    legs = {}
+
+    def run(name, p, nthreads, budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.solve(p.copy(seed=p.seed + reps), nthreads=nthreads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                break
+        legs[name] = {"sample_steps_per_s": p.S * p.T * reps / el, "solves_per_s": reps / el,
+                      "threads": nthreads, "updates": reps, "seconds": el, "S": p.S, "T": p.T,
+                      "n_obs": p.n_obs}
+
+    share = seconds / 6.0
+    run("c2_update_all_threads", prob, threads, share)
+    run("c2_update_1_thread", prob, 1, share)
+    c1 = W.config1()
+    run("c1_update_all_threads", c1, threads, share / 2)
+    run("c1_update_1_thread", c1, 1, share / 2)
+    big = W.config5().copy(S=512)
+    run("c5_512_samples_all_threads", big, threads, share)
+    run("c5_512_samples_1_thread", big, 1, share)
+    v = legs["c2_update_all_threads"]["sample_steps_per_s"]
     return {"value": v, "unit": "sample-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} updates of the reverse-parking problem with S=1024 of its 8192 samples "
-                      f"(T=50, 8 obstacles) in {el:.1f} s on {threads} threads"}
+            "sample": f"{legs['c2_update_all_threads']['updates']} full updates of the reverse-parking problem "
+                      f"(S=8192, T=50, 8 obstacles) on {threads} threads; also one thread, the c1 update "
+                      f"and 512 samples of the S=65536, T=100, 32-obstacle update (legs)",
+            "host": cpu, "legs": legs}
 
 
 if __name__ == "__main__":

@@ -49,6 +49,8 @@ extern "C" {
 #define BRMPPI_EDEVICE (-6)       /* a HIP call failed */
 #define BRMPPI_ETIMEDOUT (-7)     /* brmppi_wait deadline passed */
 #define BRMPPI_ESTATE (-8)        /* missing state (no path / no warm start) */
+#define BRMPPI_ECANCELED (-9)     /* served form: the context was destroyed before the
+                                     request was admitted */
 
 /* ---- limits ------------------------------------------------------------- */
 #define BRMPPI_MAX_OBS 32         /* obstacles per solve */
@@ -148,7 +150,8 @@ typedef struct {
   uint32_t flags;             /* BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT |
                                  BRMPPI_ADVANCE_PLANT | BRMPPI_COLLISION_PENALTY |
                                  BRMPPI_HITCH_QP */
-  const brmppi_params* params;/* required */
+  const brmppi_params* params;/* NULL = the controller's parameters (brmppi_set_params;
+                                 brmppi_default_params until set) */
 } brmppi_problem;
 
 typedef struct {
@@ -174,6 +177,33 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out);
  * arena is the caller's and is not touched afterwards. */
 int brmppi_destroy(brmppi_ctx* ctx);
 const char* brmppi_last_error(void);
+
+/* Counters of a context (host bookkeeping; no device work). */
+typedef struct {
+  uint64_t scratch_grows;     /* times a call had to re-allocate the solve scratch in the arena */
+  uint64_t pinned_grows;      /* times a call had to re-allocate a pinned staging buffer
+                                 (hipHostFree + hipHostMalloc); staging of 1 MiB per stream is
+                                 allocated at create */
+  uint64_t arena_bytes;       /* size of the caller's arena */
+  uint64_t arena_used;        /* bytes of it sub-allocated now */
+  uint64_t served_done;       /* served requests completed by the device */
+  uint64_t served_failed;     /* served requests that failed before or at launch */
+} brmppi_info;
+int brmppi_get_info(brmppi_ctx* ctx, brmppi_info* out);
+
+/* ---- parameters ---------------------------------------------------------- */
+/* The library's defaults (the paper's tuned values are unpublished): the
+ * Sec. V input bounds j in [-2, 2] m/s^3, omega in [-0.9, 0.9] rad/s; a
+ * 4 m / 0.5 m / 10 m tractor-trailer, hitch limit 0.7 - 0.05 v rad, footprint
+ * disc 1 m; Ts 0.05 s; sampling noise (1.0, 0.3, 0.5) and 0.2 for the
+ * auxiliary inputs; W the inverse sampling covariance, rho 0.1; barrier rates
+ * 0.5 within [-1, 1]; Qc = Ql = 2, Qth = 1, R = 0.05, mu 0.5, nu_bar 2 m/s;
+ * w_col 1000; Q_h = W's input block, alpha_h 0.5.  Errors: EINVAL (NULL). */
+int brmppi_default_params(brmppi_params* out);
+/* Parameters a controller's problems use when their params pointer is NULL
+ * (NULL here restores the defaults).  Errors: EINVAL (out of range, non-finite
+ * or inconsistent values; nothing changed). */
+int brmppi_set_params(brmppi_ctx* ctx, uint32_t controller, const brmppi_params* params);
 
 /* ---- controller state --------------------------------------------------- */
 /* Copy a reference path zeta(psi) (Sec. IV-B) into the controller's device
@@ -271,6 +301,11 @@ int brmppi_debug_philox(brmppi_ctx* ctx, const uint32_t* ctr, const uint32_t key
  * (host, n*2) the first K normals -> out (host, n*K). */
 int brmppi_debug_normals(brmppi_ctx* ctx, uint64_t seed, uint32_t instance, const uint32_t* s_tau,
                          uint32_t n, uint32_t K, float* out);
+/* The two factors of the kernels' Box-Muller transform (Sec. III-B sampling)
+ * for n raw Philox words r (host): out[3i] = sqrt(-2 ln u), out[3i + 1] =
+ * cos(2 pi u), out[3i + 2] = sin(2 pi u), with u = ((r >> 9) + 1/2) / 2^23
+ * (host, n*3 floats).  n <= 2^24. */
+int brmppi_debug_box_muller(brmppi_ctx* ctx, const uint32_t* r, uint32_t n, float* out);
 
 #ifdef __cplusplus
 }

@@ -462,8 +462,9 @@ double orc_stage_cost(const double x[8], const double u[3], const double* path, 
 
 /* Collision-penalty baseline (Sec. V, the second MPPI baseline; the paper   */
 /* gives no formula).  READING: w_col * sum_o max(0, -h_o(x, t))^2 with h_o   */
-/* the e = 2 obstacle function of eq. (16) at the current state and time,    */
-/* added to the stage cost of every step and to the terminal cost.           */
+/* the obstacle function of eq. (16) (exponent e = 2 or 4, as the obstacle   */
+/* has it) at the current state and time, added to the stage cost of every   */
+/* step and to the terminal cost.                                            */
 double orc_collision_penalty(const double x[8], double t, const orc_obstacle* obs, int n_obs, const orc_params* p) {
   double pen = 0.0;
   for (int o = 0; o < n_obs; ++o) {

@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "brmppi.h")
 
 # return codes / flags (include/brmppi.h)
 OK, PENDING = 0, 1
-EINVAL, ENOMEM, EAGAIN, ENONFINITE, ENOTICKET, EDEVICE, ETIMEDOUT, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
+EINVAL, ENOMEM, EAGAIN, ENONFINITE, ENOTICKET, EDEVICE, ETIMEDOUT, ESTATE, ECANCELED = (
+    -1, -2, -3, -4, -5, -6, -7, -8, -9)
 GUIDANCE_OFF, HITCH_OFF, X0_RESIDENT, ADVANCE_PLANT, COLLISION_PENALTY, HITCH_QP = 1, 2, 4, 8, 16, 32
 CTX_PROFILE, CTX_PROFILE_ROLLOUT = 1, 2
 MAX_OBS, MAX_T = 32, 512
@@ -63,6 +64,11 @@ class brmppi_problem(C.Structure):
 class brmppi_stats(C.Structure):
     _fields_ = [("J_min", C.c_float), ("Z", C.c_float), ("ess", C.c_float), ("status", C.c_int32),
                 ("latency_us", C.c_double)]
+
+
+class brmppi_info(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("scratch_grows", "pinned_grows", "arena_bytes", "arena_used",
+                                          "served_done", "served_failed")]
 
 
 class brmppi_outputs(C.Structure):
@@ -112,6 +118,10 @@ def lib():
         "brmppi_profile_reset": (I, [ctx]),
         "brmppi_debug_philox": (I, [ctx, P(U32), P(U32), U32, P(U32)]),
         "brmppi_debug_normals": (I, [ctx, U64, U32, P(U32), U32, U32, P(F)]),
+        "brmppi_debug_box_muller": (I, [ctx, P(U32), U32, P(F)]),
+        "brmppi_get_info": (I, [ctx, P(brmppi_info)]),
+        "brmppi_default_params": (I, [P(brmppi_params)]),
+        "brmppi_set_params": (I, [ctx, U32, P(brmppi_params)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -146,7 +156,8 @@ def params_struct(p: dict) -> brmppi_params:
 class ProblemBuffers:
     """A brmppi_problem plus the host arrays it points to."""
 
-    def __init__(self, prob, controller=None, with_nominal=True, flags=None, seed=None, x0=None):
+    def __init__(self, prob, controller=None, with_nominal=True, flags=None, seed=None, x0=None,
+                 with_params=True):
         self.params = params_struct(prob.params)
         obs = np.ascontiguousarray(np.asarray(prob.obstacles, dtype=np.float32).reshape(-1, 8))
         self.obs = (brmppi_obstacle * max(1, obs.shape[0]))(*[brmppi_obstacle(*map(float, o)) for o in obs])
@@ -165,7 +176,7 @@ class ProblemBuffers:
         c.seed = int(prob.seed if seed is None else seed) & (2**64 - 1)
         c.instance = int(prob.instance) & 0xFFFFFFFF
         c.flags = int(prob.flags if flags is None else flags)
-        c.params = C.pointer(self.params)
+        c.params = C.pointer(self.params) if with_params else None
         self.c = c
 
 
@@ -313,6 +324,30 @@ def brmppi_debug_normals(ctx, seed, instance, s_tau, K):
                                      s_tau.ctypes.data_as(C.POINTER(C.c_uint32)), s_tau.shape[0], int(K),
                                      _fp(out)))
     return out
+
+
+def brmppi_debug_box_muller(ctx, r):
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.uint32).reshape(-1))
+    out = np.zeros((r.size, 3), np.float32)
+    check(lib().brmppi_debug_box_muller(ctx, r.ctypes.data_as(C.POINTER(C.c_uint32)), r.size, _fp(out)))
+    return out
+
+
+def brmppi_get_info(ctx) -> dict:
+    info = brmppi_info()
+    check(lib().brmppi_get_info(ctx, C.byref(info)))
+    return {k: int(getattr(info, k)) for k, _ in brmppi_info._fields_}
+
+
+def brmppi_default_params() -> dict:
+    p = brmppi_params()
+    check(lib().brmppi_default_params(C.byref(p)))
+    return {k: float(getattr(p, k)) for k in PARAM_FIELDS}
+
+
+def brmppi_set_params(ctx, controller, params):
+    ps = params_struct(params) if params is not None else None
+    return check(lib().brmppi_set_params(ctx, int(controller), C.byref(ps) if ps is not None else None))
 
 
 # ---------------------------------------------------------------------------

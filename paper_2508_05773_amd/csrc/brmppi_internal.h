@@ -83,6 +83,12 @@ __host__ __device__ inline size_t fused_lds_region(uint32_t per_tile, uint32_t T
   const size_t a = (size_t)3 * T * (per_tile + 1);
   return ((a > n_groups ? a : n_groups) + 3) / 4 * 4;
 }
+// a tile can reduce itself only when it holds whole units and the tiles cover
+// each group of kWChunk samples exactly (no tile straddles two groups, so a
+// group has ceil(units / units per tile) tiles)
+__host__ __device__ inline bool fused_tile_ok(uint32_t per_tile) {
+  return per_tile > 0 && per_tile % kUnit == 0 && kWChunk % per_tile == 0;
+}
 __host__ __device__ inline size_t fused_lds_bytes(uint32_t per_tile, uint32_t T, uint32_t n_groups) {
   return sizeof(float) * (fused_lds_region(per_tile, T, n_groups) + 2 * (size_t)per_tile + 2 * kGroupUnits) +
          16 * kGroupUnits;
@@ -97,6 +103,7 @@ hipError_t launch_philox_dump(const uint32_t* ctr, uint32_t k0, uint32_t k1, uin
                               hipStream_t stream);
 hipError_t launch_normals_dump(uint32_t seed_lo, uint32_t seed_hi, uint32_t instance, const uint32_t* s_tau,
                                uint32_t n, uint32_t K, float* out, hipStream_t stream);
+hipError_t launch_box_muller_dump(const uint32_t* r, uint32_t n, float* out, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t stream);
 // occupancy of a rollout variant for a bucket and block size (blocks per CU)
 int rollout_blocks_per_cu(int bucket, int variant, uint32_t block);

@@ -1707,6 +1707,16 @@ __global__ void k_normals_dump(uint32_t seed_lo, uint32_t seed_hi, uint32_t inst
   }
 }
 
+// the radius and the two angle factors of box_muller4 for raw words r
+__global__ void k_box_muller_dump(const uint32_t* __restrict__ r, uint32_t n, float* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float u = unif23(r[i]);
+  out[3 * (size_t)i] = bm_radius(u);
+  out[3 * (size_t)i + 1] = __builtin_amdgcn_cosf(u);
+  out[3 * (size_t)i + 2] = __builtin_amdgcn_sinf(u);
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
@@ -1828,6 +1838,13 @@ hipError_t launch_normals_dump(uint32_t seed_lo, uint32_t seed_hi, uint32_t inst
   const uint32_t b = 256, g = (n + b - 1) / b;
   if (g == 0) return hipSuccess;
   hipLaunchKernelGGL(k_normals_dump, dim3(g), dim3(b), 0, stream, seed_lo, seed_hi, instance, s_tau, n, K, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_muller_dump(const uint32_t* r, uint32_t n, float* out, hipStream_t stream) {
+  const uint32_t b = 256, g = (n + b - 1) / b;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_box_muller_dump, dim3(g), dim3(b), 0, stream, r, n, out);
   return hipGetLastError();
 }
 

@@ -108,13 +108,19 @@ class Arena {
   std::map<size_t, size_t> free_;
 };
 
-// pinned host staging buffer
+// pinned host staging buffer (allocated at create; re-allocated only when a
+// call needs more, which `grows` counts)
+constexpr size_t kPinnedInit = size_t(1) << 20;
 struct Pinned {
   char* ptr = nullptr;
   size_t bytes = 0;
+  uint64_t grows = 0;
   int ensure(size_t n) {
     if (n <= bytes) return 0;
-    if (ptr) (void)hipHostFree(ptr);
+    if (ptr) {
+      (void)hipHostFree(ptr);
+      ++grows;
+    }
     ptr = nullptr;
     bytes = 0;
     n = round_up(std::max<size_t>(n, 4096), 4096);
@@ -140,6 +146,7 @@ struct Controller {
   uint32_t warm_T = 0;        // length of the resident warm start, 0 = none
   bool plant_set = false;
   bool busy = false;          // a served request is in flight
+  brmppi_params params{};     // used by problems whose params pointer is NULL
 };
 
 // layout of one instance's scratch inside a block (off_out: [stats(4) | u_new(3T)]
@@ -225,8 +232,10 @@ uint32_t reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu) {
 // half of the context's arena.  Beyond it the solve draws its normals in the
 // rollout kernel (one lane per sample).
 constexpr size_t kMaxNoiseBytes = size_t(2) << 30;
-// closed loop: normals of up to this many bytes are drawn per noise launch
+// closed loop: normals of up to this many bytes are drawn per noise launch,
+// and at most this many updates share one descriptor upload and noise launch
 constexpr size_t kClosedLoopNoiseBytes = size_t(256) << 20;
+constexpr uint32_t kLoopChunk = 16;
 
 struct Profile {
   double ms[5] = {0, 0, 0, 0, 0};
@@ -297,9 +306,11 @@ struct brmppi_ctx {
   Block counters_blk;           // BatchCounters per stream + spare
   BatchCounters* counters = nullptr;
 
-  // blocking-path scratch (cached)
+  // blocking-path scratch (cached; re-allocated only when a call needs more)
   Block scratch;
+  uint64_t scratch_grows = 0;
   Pinned pin;                   // blocking staging
+  hipEvent_t loop_ev[2] = {nullptr, nullptr};   // closed loop: completion of each staging half
   // graph cache for the batched form
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -321,9 +332,49 @@ struct brmppi_ctx {
   Pinned slot_pin[4];
   bool slot_busy[4] = {false, false, false, false};
   size_t n_active = 0;          // queued + running requests
+  uint64_t served_done = 0, served_failed = 0;
+
+  // host resources (also on a failed create); device memory is the caller's
+  ~brmppi_ctx() {
+    pin.release();
+    for (auto& p : slot_pin) p.release();
+    for (auto& e : loop_ev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  }
 };
 
 namespace {
+
+// Defaults of every tuning parameter (the paper's tuned values are
+// unpublished): the Sec. V input bounds j in [-2, 2] m/s^3 and omega in
+// [-0.9, 0.9] rad/s; a 4 m / 0.5 m / 10 m tractor-trailer with the hitch limit
+// 0.7 - 0.05 v rad and a 1 m footprint disc; Ts = 0.05 s; sampling noise
+// (1.0, 0.3, 0.5) for (j, omega, nu) and 0.2 for the auxiliary inputs; W the
+// inverse sampling covariance, rho = 0.1; barrier rates starting at 0.5 within
+// [-1, 1]; contouring weights Qc = Ql = 2, heading weights 1, effort 0.05,
+// progress weight 0.5 toward 2 m/s; collision-penalty weight 1000; hitch QP
+// with Q_h = W's input block and alpha_h = 0.5.
+brmppi_params default_params() {
+  brmppi_params P{};
+  P.Ts = 0.05f; P.l1 = 4.0f; P.lh = 0.5f; P.l2 = 10.0f; P.dtheta_max = 0.7f; P.kappa = 0.05f; P.r_disc = 1.0f;
+  P.Qc = 2.0f; P.Ql = 2.0f; P.Qth1 = 1.0f; P.Qth2 = 1.0f; P.R_j = 0.05f; P.R_w = 0.05f; P.mu = 0.5f;
+  P.nu_bar = 2.0f;
+  P.sigma_j = 1.0f; P.sigma_w = 0.3f; P.sigma_nu = 0.5f; P.sigma_a = 0.2f;
+  P.W_j = (float)(1.0 / (1.0 * 1.0)); P.W_w = (float)(1.0 / (0.3 * 0.3));
+  P.W_a = (float)(1.0 / (0.2 * 0.2)); P.rho = 0.1f;
+  P.j_lo = -2.0f; P.j_hi = 2.0f; P.w_lo = -0.9f; P.w_hi = 0.9f;
+  P.alpha0 = 0.5f; P.alpha_lo = -1.0f; P.alpha_hi = 1.0f;
+  P.h_eps = 1e-5f; P.w_col = 1000.0f;
+  P.qh_j = P.W_j; P.qh_w = P.W_w; P.alpha_h = 0.5f;
+  return P;
+}
+
+// the parameters a problem runs with: its own, or its controller's
+const brmppi_params& params_of(const brmppi_ctx* ctx, const brmppi_problem& p) {
+  return p.params ? *p.params : ctx->ctrl[p.controller].params;
+}
 
 // ---------------------------------------------------------------------------
 // validation
@@ -335,6 +386,16 @@ bool finite_params(const brmppi_params& p) {
   return true;
 }
 
+int validate_params(const brmppi_params& P) {
+  if (!finite_params(P)) return fail(BRMPPI_EINVAL, "non-finite parameter");
+  if (!(P.Ts > 0) || !(P.l1 > 0) || !(P.l2 > 0) || !(P.h_eps > 0))
+    return fail(BRMPPI_EINVAL, "Ts, l1, l2 and h_eps must be positive");
+  if (!(P.W_j + P.rho > 0) || !(P.W_w + P.rho > 0) || !(P.W_a + P.rho > 0) || P.rho < 0 || P.W_j < 0 ||
+      P.W_w < 0 || P.W_a < 0)
+    return fail(BRMPPI_EINVAL, "projection weights must be >= 0 with W + rho > 0");
+  return BRMPPI_OK;
+}
+
 int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (!ctx || !p) return fail(BRMPPI_EINVAL, "null context or problem");
   if (p->controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
@@ -342,7 +403,6 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if (p->T < 1 || p->T > BRMPPI_MAX_T) return fail(BRMPPI_EINVAL, "T out of range");
   if (p->n_obs > BRMPPI_MAX_OBS) return fail(BRMPPI_EINVAL, "too many obstacles");
   if (p->n_obs > 0 && !p->obs) return fail(BRMPPI_EINVAL, "obstacles pointer is NULL");
-  if (!p->params) return fail(BRMPPI_EINVAL, "params pointer is NULL");
   if (p->flags & ~(BRMPPI_GUIDANCE_OFF | BRMPPI_HITCH_OFF | BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT |
                    BRMPPI_COLLISION_PENALTY | BRMPPI_HITCH_QP))
     return fail(BRMPPI_EINVAL, "unknown flags");
@@ -350,13 +410,8 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
     return fail(BRMPPI_EINVAL, "BRMPPI_HITCH_QP acts on the plant step (BRMPPI_ADVANCE_PLANT)");
   if ((p->flags & BRMPPI_ADVANCE_PLANT) && !(p->flags & BRMPPI_X0_RESIDENT))
     return fail(BRMPPI_EINVAL, "BRMPPI_ADVANCE_PLANT needs BRMPPI_X0_RESIDENT");
-  const brmppi_params& P = *p->params;
-  if (!finite_params(P)) return fail(BRMPPI_EINVAL, "non-finite parameter");
-  if (!(P.Ts > 0) || !(P.l1 > 0) || !(P.l2 > 0) || !(P.h_eps > 0))
-    return fail(BRMPPI_EINVAL, "Ts, l1, l2 and h_eps must be positive");
-  if (!(P.W_j + P.rho > 0) || !(P.W_w + P.rho > 0) || !(P.W_a + P.rho > 0) || P.rho < 0 || P.W_j < 0 ||
-      P.W_w < 0 || P.W_a < 0)
-    return fail(BRMPPI_EINVAL, "projection weights must be >= 0 with W + rho > 0");
+  const brmppi_params& P = params_of(ctx, *p);
+  if (int rc = validate_params(P)) return rc;
   if (!(p->lambda > 0) || !std::isfinite(p->lambda)) return fail(BRMPPI_EINVAL, "lambda must be positive");
   if ((p->flags & BRMPPI_HITCH_QP) && (!(P.qh_j > 0) || !(P.qh_w > 0) || !(P.alpha_h > 0)))
     return fail(BRMPPI_EINVAL, "BRMPPI_HITCH_QP needs qh_j, qh_w and alpha_h positive");
@@ -388,7 +443,7 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
                uint32_t seed_offset, const float* unom_dev, uint32_t* counter, float* out, bool fused = false,
                bool ustar_global = true) {
   std::memset(&d, 0, sizeof(d));
-  d.prm = *p.params;
+  d.prm = p.params ? *p.params : c.params;
   d.lambda = p.lambda;
   d.inv_lambda = 1.0f / p.lambda;
   for (int k = 0; k < 8; ++k) d.x0[k] = p.x0[k];
@@ -449,7 +504,7 @@ LaunchShape plain_shape(brmppi_ctx* ctx, const brmppi_problem& p) {
 // not whole units or do not fit (k_reduce then reduces from HBM)
 size_t fused_lds(const brmppi_problem& p, const LaunchShape& sh) {
   const uint32_t per_tile = sh.block / (uint32_t)variant_lanes(sh.variant);
-  if (per_tile % kUnit) return 0;
+  if (!fused_tile_ok(per_tile)) return 0;
   const size_t b = fused_lds_bytes(per_tile, p.T, (p.S + kWChunk - 1) / kWChunk);
   return b <= kFusedLdsMax ? b : 0;
 }
@@ -539,6 +594,7 @@ int enqueue_single(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, con
 
 int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
   if (ctx->scratch.bytes >= bytes) return 0;
+  if (ctx->scratch.ptr) ++ctx->scratch_grows;
   ctx->arena.release(ctx->scratch);
   ctx->scratch = ctx->arena.alloc(bytes);
   if (!ctx->scratch.ptr) return fail(BRMPPI_ENOMEM, "solve scratch does not fit in the arena");
@@ -910,98 +966,131 @@ int closed_loop_locked(brmppi_ctx* ctx, const brmppi_problem* p0, uint32_t n_up,
   if (p0->controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
   Controller& c = ctx->ctrl[p0->controller];
   brmppi_problem p = *p0;
+  if (!p.params) p.params = &c.params;
   const bool resume = (p.flags & BRMPPI_X0_RESIDENT) != 0;
   if (!resume) {
     if (!c.plant) return fail(BRMPPI_ESTATE, "controller has no path (brmppi_set_path)");
     for (int k = 0; k < 8; ++k)
       if (!std::isfinite(p.x0[k])) return fail(BRMPPI_EINVAL, "non-finite x0");
-    c.plant_set = true;  // provisional, for validate(); restored below on error
   }
+  const bool plant_was_set = c.plant_set;
+  if (!resume) c.plant_set = true;  // provisional (the caller's x0 is uploaded below), for validate()
   p.flags |= BRMPPI_X0_RESIDENT | BRMPPI_ADVANCE_PLANT;
   int rc = validate(ctx, &p);
-  if (rc) {
-    if (!resume) c.plant_set = false;
-    return rc;
-  }
+  c.plant_set = plant_was_set;
+  if (rc) return rc;
   const LaunchShape sh = plain_shape(ctx, p);
   const ScratchLayout L = plain_layout(ctx, p, sh);
   const size_t lds = fused_lds(p, sh);
-  // device: [scratch | descriptors of every update | counters | nominal | logs];
-  // descriptors, counters and nominal sequence travel in one upload
-  const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
-  const size_t in_off = L.bytes;
-  const size_t ctr_rel = desc_bytes * n_up;
-  const size_t unom_rel = ctr_rel + counter_bytes(L.n_wchunk);
-  const size_t in_bytes = unom_rel + (p.u_nom ? sizeof(float) * 3 * p.T : 0);
-  const size_t log_off = in_off + round_up(in_bytes, 256);
-  const size_t log_end = log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256) +
-                         round_up(sizeof(float) * 3 * n_up, 256);
-  // Normals come in chunks of C updates, one noise launch per chunk (slot
-  // k mod C of one chunk-sized region).  Drawing the next chunk on a second
-  // stream while a chunk runs was measured slower: the noise waves delay the
-  // rollout's, each of which is on the critical path of its update.
+  // The updates run in chunks of C: one descriptor upload per chunk and, when
+  // the launch shape reads precomputed normals, one noise launch per chunk
+  // (slot i of a chunk-sized noise region for its i-th update).  Descriptors
+  // and logs go through two staging halves used in turn, so the host prepares
+  // chunk j + 2 only once chunk j has completed and the device never waits
+  // for the host.  Nothing here depends on n_up: a loop of any length reuses
+  // the scratch and staging of a shorter one.  (Drawing the next chunk's
+  // normals on a second stream while a chunk runs was measured slower: the
+  // noise waves delay the rollout's, each of which is on the critical path of
+  // its update.)
   const bool pre = variant_pre(sh.variant);
-  const size_t noise_bytes = round_up((size_t)L.n_normals * p.T * L.S_pad * sizeof(float), 256);
-  uint32_t C = 1;
-  if (pre) C = (uint32_t)std::max<size_t>(1, std::min<size_t>({16, n_up, kClosedLoopNoiseBytes / noise_bytes}));
-  const size_t noise_off = log_end;
-  const size_t need = log_end + (pre ? C * noise_bytes : 0);
+  const size_t noise_bytes = pre ? round_up((size_t)L.n_normals * p.T * L.S_pad * sizeof(float), 256) : 0;
+  uint32_t C = kLoopChunk;
+  if (pre) {
+    const size_t cap = std::min(kClosedLoopNoiseBytes, ctx->arena.size() / 2);
+    C = (uint32_t)std::max<size_t>(1, std::min<size_t>(kLoopChunk, cap / noise_bytes));
+  }
+  const bool logs = x_out || u_applied;
+  const size_t desc_bytes = round_up(sizeof(SolveDesc), 256);
+  const size_t unom_bytes = p.u_nom ? sizeof(float) * 3 * p.T : 0;
+  const size_t xlog_bytes = round_up(sizeof(double) * 8 * C, 256);
+  const size_t half_bytes = desc_bytes * C + xlog_bytes + round_up(sizeof(float) * 3 * C, 256);
+  // device: [scratch | counters (zero) | nominal | half 0 | half 1 | normals of C updates]
+  // pinned: [counters | nominal | half 0 | half 1 | start state]; a half holds
+  // the chunk's descriptors, then its plant states and applied inputs
+  const size_t ctr_rel = 0;
+  const size_t unom_rel = counter_bytes(L.n_wchunk);
+  const size_t head_bytes = unom_rel + unom_bytes;
+  const size_t half_rel = round_up(head_bytes, 256);
+  const size_t x0_rel = half_rel + 2 * half_bytes;
+  const size_t in_off = L.bytes;
+  const size_t noise_off = in_off + x0_rel;
+  const size_t need = noise_off + (pre ? C * noise_bytes : 0);
   if ((rc = ensure_scratch(ctx, need))) return rc;
+  if ((rc = ctx->pin.ensure(x0_rel + 256))) return rc;
   char* base = ctx->scratch.ptr;
-  hipStream_t s = ctx->streams[0];
-  const size_t pin_need = round_up(in_bytes, 256) + 256 + sizeof(double) * 8 * (n_up + 1) +
-                          sizeof(float) * 3 * n_up;
-  if ((rc = ctx->pin.ensure(pin_need))) return rc;
   char* pin = ctx->pin.ptr;
-  double* d_xlog = reinterpret_cast<double*>(base + log_off);
-  float* d_ulog = reinterpret_cast<float*>(base + log_off + round_up(sizeof(double) * 8 * (n_up + 1), 256));
+  hipStream_t s = ctx->streams[0];
   uint32_t* d_ctr = reinterpret_cast<uint32_t*>(base + in_off + ctr_rel);
   const float* d_unom = reinterpret_cast<const float*>(base + in_off + unom_rel);
   float* d_out = reinterpret_cast<float*>(base + L.off_out);
-  for (uint32_t k = 0; k < n_up; ++k) {
-    SolveDesc* hd = reinterpret_cast<SolveDesc*>(pin + desc_bytes * k);
-    // only the first update reads the caller's sequence; later ones the shifted result
-    fill_desc(*hd, p, c, L, base, k, k == 0 ? d_unom : nullptr, d_ctr, d_out, lds > 0, false);
-    if (pre) hd->noise = reinterpret_cast<float*>(base + noise_off + (k % C) * noise_bytes);
-  }
+  auto half_dev = [&](int h) { return base + in_off + half_rel + h * half_bytes; };
+  auto half_pin = [&](int h) { return pin + half_rel + h * half_bytes; };
+
   std::memset(pin + ctr_rel, 0, unom_rel - ctr_rel);
-  if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, sizeof(float) * 3 * p.T);
-  char* pin_x = pin + round_up(in_bytes, 256);
+  if (p.u_nom) std::memcpy(pin + unom_rel, p.u_nom, unom_bytes);
+  double* pin_x0 = reinterpret_cast<double*>(pin + x0_rel);
   if (!resume) {
-    double* px = reinterpret_cast<double*>(pin_x);
-    for (int k = 0; k < 8; ++k) px[k] = (double)p0->x0[k];
-    HIPCHK(hipMemcpyAsync(c.plant, px, sizeof(double) * 8, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 8; ++k) pin_x0[k] = (double)p0->x0[k];
+    HIPCHK(hipMemcpyAsync(c.plant, pin_x0, sizeof(double) * 8, hipMemcpyHostToDevice, s));
+  } else if (x_out) {
+    HIPCHK(hipMemcpyAsync(pin_x0, c.plant, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
   }
-  HIPCHK(hipMemcpyAsync(base + in_off, pin, in_bytes, hipMemcpyHostToDevice, s));
-  if (x_out) HIPCHK(hipMemcpyAsync(d_xlog, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
-  auto desc_at = [&](uint32_t k) {
-    return reinterpret_cast<const SolveDesc*>(base + L.bytes + desc_bytes * k);
-  };
-  for (uint32_t k = 0; k < n_up; ++k) {
-    const SolveDesc* dd = desc_at(k);
-    if (!pre) {
-      if ((rc = enqueue_single(ctx, s, dd, p, L, sh, lds))) return rc;   // includes the plant step
-    } else {
-      if (k % C == 0) {
-        const uint32_t cnt = std::min(C, n_up - k);
-        rc = timed(ctx, s, 4, [&] { return launch_noise(dd, desc_bytes, cnt, p.S, p.T, L.n_normals, s); });
-        if (rc) return rc;
-      }
-      if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh, lds))) return rc;
-    }
-    if (x_out) HIPCHK(hipMemcpyAsync(d_xlog + 8 * (k + 1), c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + in_off, pin, head_bytes, hipMemcpyHostToDevice, s));
+  const uint32_t n_chunks = (n_up + C - 1) / C;
+  // copy the logs of chunk j (complete) from its staging half to the caller
+  auto take_logs = [&](uint32_t j) {
+    const char* hp = half_pin((int)(j % 2));
+    const uint32_t k0 = j * C, cnt = std::min(C, n_up - k0);
+    if (x_out)
+      std::memcpy(x_out + 8 * (size_t)(k0 + 1), hp + desc_bytes * C, sizeof(double) * 8 * cnt);
     if (u_applied)
-      HIPCHK(hipMemcpyAsync(d_ulog + 3 * k, base + L.off_out + 4 * sizeof(float), sizeof(float) * 3,
-                            hipMemcpyDeviceToDevice, s));
+      std::memcpy(u_applied + 3 * (size_t)k0, hp + desc_bytes * C + xlog_bytes, sizeof(float) * 3 * cnt);
+  };
+  for (uint32_t j = 0; j < n_chunks; ++j) {
+    const int h = (int)(j % 2);
+    if (j >= 2) {
+      HIPCHK(hipEventSynchronize(ctx->loop_ev[h]));
+      if (logs) take_logs(j - 2);
+    }
+    const uint32_t k0 = j * C, cnt = std::min(C, n_up - k0);
+    char* hp = half_pin(h);
+    char* hd = half_dev(h);
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const uint32_t k = k0 + i;
+      SolveDesc* d = reinterpret_cast<SolveDesc*>(hp + desc_bytes * i);
+      // only the first update reads the caller's sequence; later ones the shifted result
+      fill_desc(*d, p, c, L, base, k, (k == 0 && p.u_nom) ? d_unom : nullptr, d_ctr, d_out, lds > 0, false);
+      if (pre) d->noise = reinterpret_cast<float*>(base + noise_off + i * noise_bytes);
+    }
+    HIPCHK(hipMemcpyAsync(hd, hp, desc_bytes * cnt, hipMemcpyHostToDevice, s));
+    const SolveDesc* first = reinterpret_cast<const SolveDesc*>(hd);
+    if (pre) {
+      rc = timed(ctx, s, 4, [&] { return launch_noise(first, desc_bytes, cnt, p.S, p.T, L.n_normals, s); });
+      if (rc) return rc;
+    }
+    double* xlog = reinterpret_cast<double*>(hd + desc_bytes * C);
+    float* ulog = reinterpret_cast<float*>(hd + desc_bytes * C + xlog_bytes);
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const SolveDesc* dd = reinterpret_cast<const SolveDesc*>(hd + desc_bytes * i);
+      if (!pre) {
+        if ((rc = enqueue_single(ctx, s, dd, p, L, sh, lds))) return rc;   // includes the plant step
+      } else {
+        if ((rc = enqueue_rollout_reduce(ctx, s, dd, p, L, sh, lds))) return rc;
+      }
+      if (x_out) HIPCHK(hipMemcpyAsync(xlog + 8 * i, c.plant, sizeof(double) * 8, hipMemcpyDeviceToDevice, s));
+      if (u_applied) HIPCHK(hipMemcpyAsync(ulog + 3 * i, d_out + 4, sizeof(float) * 3, hipMemcpyDeviceToDevice, s));
+    }
+    if (logs)
+      HIPCHK(hipMemcpyAsync(hp + desc_bytes * C, hd + desc_bytes * C, half_bytes - desc_bytes * C,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ctx->loop_ev[h], s));
   }
-  double* hx = reinterpret_cast<double*>(pin_x + 256);
-  float* hu = reinterpret_cast<float*>(hx + 8 * (n_up + 1));
-  if (x_out) HIPCHK(hipMemcpyAsync(hx, d_xlog, sizeof(double) * 8 * (n_up + 1), hipMemcpyDeviceToHost, s));
-  if (u_applied) HIPCHK(hipMemcpyAsync(hu, d_ulog, sizeof(float) * 3 * n_up, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   collect_timing(ctx);
-  if (x_out) std::memcpy(x_out, hx, sizeof(double) * 8 * (n_up + 1));
-  if (u_applied) std::memcpy(u_applied, hu, sizeof(float) * 3 * n_up);
+  if (logs) {
+    for (uint32_t j = n_chunks >= 2 ? n_chunks - 2 : 0; j < n_chunks; ++j) take_logs(j);
+    if (x_out) std::memcpy(x_out, pin_x0, sizeof(double) * 8);
+  }
   c.plant_set = true;
   c.warm_T = p.T;
   return BRMPPI_OK;
@@ -1064,19 +1153,30 @@ void retire_served(brmppi_ctx* ctx, ServedBatch& b) {
     Controller& c = ctx->ctrl[r->prob.controller];
     c.busy = false;
     if (r->status == BRMPPI_OK) c.warm_T = r->prob.T;
+    ++ctx->served_done;
   }
   ctx->arena.release(b.mem);
   ctx->slot_busy[b.slot] = false;
 }
 
+void fail_request(brmppi_ctx* ctx, Request* r, int code) {
+  r->status = code;
+  r->st.status = code;
+  r->done = true;
+  ++ctx->served_failed;
+}
+
+// fail every request of a batch; work of it that may already be enqueued on
+// the slot's stream finishes before its memory goes back to the arena
 void fail_batch(brmppi_ctx* ctx, ServedBatch& b, int code) {
   for (Request* r : b.reqs) {
-    r->status = code;
-    r->st.status = code;
-    r->done = true;
+    fail_request(ctx, r, code);
     ctx->ctrl[r->prob.controller].busy = false;
   }
+  if (b.mem.ptr) (void)hipStreamSynchronize(ctx->streams[b.slot]);
   ctx->arena.release(b.mem);
+  if (b.done_ev) (void)hipEventDestroy(b.done_ev);
+  b.done_ev = nullptr;
   ctx->slot_busy[b.slot] = false;
 }
 
@@ -1094,7 +1194,7 @@ void request_loop(brmppi_ctx* ctx) {
         ctx->inflight.erase(ctx->inflight.begin() + i);
         progressed = true;
       } else if (q != hipErrorNotReady) {
-        fail_batch(ctx, ctx->inflight[i], BRMPPI_EDEVICE);
+        fail_batch(ctx, ctx->inflight[i], BRMPPI_EDEVICE);   // also destroys its event
         ctx->inflight.erase(ctx->inflight.begin() + i);
         progressed = true;
       } else {
@@ -1102,6 +1202,13 @@ void request_loop(brmppi_ctx* ctx) {
       }
     }
     if (progressed) ctx->cv.notify_all();
+    // a destroyed context runs nothing more: queued requests fail, batches in
+    // flight drain
+    if (!ctx->running && !ctx->queue.empty()) {
+      for (Request* r : ctx->queue) fail_request(ctx, r, BRMPPI_ECANCELED);
+      ctx->queue.clear();
+      ctx->cv.notify_all();
+    }
     // admit queued requests into a new batch on a free stream slot
     int slot = -1;
     for (uint32_t k = 0; k < ctx->n_streams; ++k)
@@ -1126,15 +1233,21 @@ void request_loop(brmppi_ctx* ctx) {
         if (!r->prob.u_nom && c.warm_T != r->prob.T) {
           // every earlier request of this controller has finished and none left
           // a warm start of length T
-          r->status = BRMPPI_ESTATE;
-          r->st.status = BRMPPI_ESTATE;
-          r->done = true;
+          fail_request(ctx, r, BRMPPI_ESTATE);
           it = ctx->queue.erase(it);
           progressed = true;
           continue;
         }
         const size_t fp = request_footprint(r->prob);
         if (!ctx->arena.fits(budget_bytes + fp)) {
+          if (b.reqs.empty() && ctx->inflight.empty()) {
+            // nothing runs that could free memory, and the context's persistent
+            // allocations never shrink: this request can never be admitted
+            fail_request(ctx, r, BRMPPI_ENOMEM);
+            it = ctx->queue.erase(it);
+            progressed = true;
+            continue;
+          }
           taken[r->prob.controller] = 1;
           ++it;
           continue;
@@ -1150,8 +1263,9 @@ void request_loop(brmppi_ctx* ctx) {
         ctx->slot_busy[slot] = true;
         const int rc = launch_served(ctx, b);
         if (rc != BRMPPI_OK) {
-          if (rc == BRMPPI_ENOMEM && b.mem.ptr == nullptr) {
-            // could not get the packed block: requeue at the front and retry later
+          if (rc == BRMPPI_ENOMEM && b.mem.ptr == nullptr && !ctx->inflight.empty()) {
+            // could not get the packed block: requeue at the front and retry once
+            // a batch in flight has returned its memory
             for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) {
               ctx->ctrl[(*it)->prob.controller].busy = false;
               ctx->queue.push_front(*it);
@@ -1180,9 +1294,9 @@ void request_loop(brmppi_ctx* ctx) {
   }
 }
 
-int copy_problem(Request& r, const brmppi_problem* p) {
+int copy_problem(const brmppi_ctx* ctx, Request& r, const brmppi_problem* p) {
   r.prob = *p;
-  r.params = *p->params;
+  r.params = params_of(ctx, *p);
   r.prob.params = &r.params;
   r.obs.assign(p->obs, p->obs + p->n_obs);
   r.prob.obs = r.obs.empty() ? nullptr : r.obs.data();
@@ -1279,6 +1393,13 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
     ctx->shape[bi][3] = LaunchShape{128, 0};
   }
   ctx->ctrl.resize(cfg->max_controllers);
+  const brmppi_params defaults = default_params();
+  for (Controller& c : ctx->ctrl) c.params = defaults;
+  // staging buffers and the closed loop's events exist for the context's life
+  if (int rc = ctx->pin.ensure(kPinnedInit)) return rc;
+  for (uint32_t k = 0; k < cfg->n_streams; ++k)
+    if (int rc = ctx->slot_pin[k].ensure(kPinnedInit)) return rc;
+  for (auto& e : ctx->loop_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   ctx->counters_blk = ctx->arena.alloc(sizeof(BatchCounters) * 5);
   if (!ctx->counters_blk.ptr) return fail(BRMPPI_ENOMEM, "arena too small");
   ctx->counters = reinterpret_cast<BatchCounters*>(ctx->counters_blk.ptr);
@@ -1308,9 +1429,37 @@ int brmppi_destroy(brmppi_ctx* ctx) {
   drop_graph(ctx);
   collect_timing(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  ctx->pin.release();
-  for (auto& p : ctx->slot_pin) p.release();
   delete ctx;
+  return BRMPPI_OK;
+}
+
+int brmppi_get_info(brmppi_ctx* ctx, brmppi_info* out) {
+  if (!ctx || !out) return fail(BRMPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  out->scratch_grows = ctx->scratch_grows;
+  uint64_t pg = ctx->pin.grows;
+  for (const auto& p : ctx->slot_pin) pg += p.grows;
+  out->pinned_grows = pg;
+  out->arena_bytes = ctx->arena.size();
+  out->arena_used = ctx->arena.used();
+  out->served_done = ctx->served_done;
+  out->served_failed = ctx->served_failed;
+  return BRMPPI_OK;
+}
+
+int brmppi_default_params(brmppi_params* out) {
+  if (!out) return fail(BRMPPI_EINVAL, "null argument");
+  *out = default_params();
+  return BRMPPI_OK;
+}
+
+int brmppi_set_params(brmppi_ctx* ctx, uint32_t controller, const brmppi_params* params) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (controller >= ctx->ctrl.size()) return fail(BRMPPI_EINVAL, "controller id out of range");
+  const brmppi_params P = params ? *params : default_params();
+  if (int rc = validate_params(P)) return rc;
+  ctx->ctrl[controller].params = P;
   return BRMPPI_OK;
 }
 
@@ -1452,7 +1601,7 @@ int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket) {
   if (ctx->n_active >= ctx->max_inflight) return fail(BRMPPI_EAGAIN, "max_inflight requests queued");
   std::unique_ptr<Request> r(new Request());
   r->ticket = ctx->next_ticket++;
-  copy_problem(*r, p);
+  copy_problem(ctx, *r, p);
   r->t_submit = Clock::now();
   Request* raw = r.get();
   ctx->reqs[raw->ticket] = std::move(r);
@@ -1617,7 +1766,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
           // time what a plain solve would run: fused epilogue where the tiles
           // are whole units, else the rollout plus k_reduce
           size_t lds = 0;
-          if (per_tile % kUnit == 0) {
+          if (fused_tile_ok(per_tile)) {
             lds = fused_lds_bytes(per_tile, T, L.n_wchunk);
             if (lds > kFusedLdsMax) lds = 0;
           }
@@ -1732,6 +1881,26 @@ int brmppi_debug_normals(brmppi_ctx* ctx, uint64_t seed, uint32_t instance, cons
     if (e == hipSuccess)
       e = launch_normals_dump((uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), instance, d_in, n, K, d_out, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(float) * (size_t)n * K, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(BRMPPI_EDEVICE, hipGetErrorString(e));
+  } while (0);
+  ctx->arena.release(b);
+  return rc;
+}
+
+int brmppi_debug_box_muller(brmppi_ctx* ctx, const uint32_t* r, uint32_t n, float* out) {
+  if (!ctx || !r || !out || n == 0 || n > (1u << 24)) return fail(BRMPPI_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Block b = ctx->arena.alloc(round_up(sizeof(uint32_t) * (size_t)n, 256) + sizeof(float) * 3 * (size_t)n);
+  if (!b.ptr) return fail(BRMPPI_ENOMEM, "debug buffer does not fit");
+  uint32_t* d_in = reinterpret_cast<uint32_t*>(b.ptr);
+  float* d_out = reinterpret_cast<float*>(b.ptr + round_up(sizeof(uint32_t) * (size_t)n, 256));
+  hipStream_t s = ctx->streams[0];
+  int rc = BRMPPI_OK;
+  do {
+    hipError_t e = hipMemcpyAsync(d_in, r, sizeof(uint32_t) * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_box_muller_dump(d_in, n, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, sizeof(float) * 3 * (size_t)n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = fail(BRMPPI_EDEVICE, hipGetErrorString(e));
   } while (0);

@@ -6,6 +6,7 @@ import os
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 from paper_2508_05773_amd import brmppi as B
@@ -47,6 +48,9 @@ int main(void) {
   F(brmppi_stats, J_min) F(brmppi_stats, status) F(brmppi_stats, latency_us)
   printf("brmppi_outputs %zu\n", sizeof(brmppi_outputs));
   F(brmppi_outputs, u_out) F(brmppi_outputs, J_out) F(brmppi_outputs, useq_out)
+  printf("brmppi_info %zu\n", sizeof(brmppi_info));
+  F(brmppi_info, scratch_grows) F(brmppi_info, pinned_grows) F(brmppi_info, arena_used)
+  F(brmppi_info, served_failed)
   return 0;
 }
 """
@@ -64,7 +68,7 @@ def test_struct_layouts_match_header():
         got[k] = int(v)
     cls = {"brmppi_config": B.brmppi_config, "brmppi_params": B.brmppi_params,
            "brmppi_obstacle": B.brmppi_obstacle, "brmppi_problem": B.brmppi_problem,
-           "brmppi_stats": B.brmppi_stats, "brmppi_outputs": B.brmppi_outputs}
+           "brmppi_stats": B.brmppi_stats, "brmppi_outputs": B.brmppi_outputs, "brmppi_info": B.brmppi_info}
     for k, v in got.items():
         if "." in k:
             t, f = k.split(".")
@@ -98,3 +102,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         B.lib()
+
+
+def test_default_params_without_a_device():
+    """brmppi_default_params needs no context: the library's defaults equal the
+    workloads' parameter set at Ts = 0.05 s (the values used by every
+    benchmark configuration but c1)"""
+    from paper_2508_05773_amd import workloads as W
+    got = B.brmppi_default_params()
+    want = W.make_params(0.05)
+    for k in B.PARAM_FIELDS:
+        assert np.float32(got[k]) == np.float32(want[k]), k
+    assert B.lib().brmppi_default_params(None) == B.EINVAL
+    assert B.lib().brmppi_set_params(None, 0, None) == B.EINVAL
+    assert B.lib().brmppi_get_info(None, None) == B.EINVAL

@@ -4,8 +4,10 @@
   bitwise, on uneven instances; every graph replay == the eager launch;
 - served: a request's result is bitwise the same alone and inside a mix of
   concurrent requests; per-controller ordering and warm starts hold;
-- closed loop on the device: the first update equals a plain solve, and the
-  FP64 plant step matches the oracle's plant.
+- closed loop on the device: the first update equals a plain solve, and K
+  updates match an oracle closed loop run from the same start;
+- launch shapes, the parameter defaults, buffer reuse and the served form's
+  admission errors.
 """
 import sys
 import time
@@ -169,19 +171,49 @@ def test_served_closed_loop_on_device(ctx):
     assert np.array_equal(B.brmppi_get_state(ctx.h, 403), x_cl[-1])
 
 
-def test_closed_loop_matches_plain_and_oracle_plant(ctx):
-    from oracle import oracle as O
+def test_closed_loop_matches_plain(ctx):
+    """the first update of the device closed loop equals a plain solve"""
     p = W.config2().copy(S=2048, T=30)
     ctx.set_path(404, p.path, p.ds)
     ctx.set_path(405, p.path, p.ds)
-    K = 4
-    x_cl, u_cl = B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=404), K)
+    x_cl, u_cl = B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=404), 3)
     assert np.all(np.isfinite(x_cl))
     u0, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=405))
     assert np.array_equal(u0[0], u_cl[0])
+
+
+@pytest.mark.parametrize("K,chunk_crossing", [(6, False), (35, True)])
+def test_closed_loop_matches_oracle_loop(ctx, K, chunk_crossing):
+    """K device-resident receding-horizon updates against an oracle closed loop
+    run from the same start: oracle update k solves from the oracle's own plant
+    state and warm start with seed + k, then the oracle plant steps by its first
+    input (clamped to the input bounds) and the warm start shifts.  Every applied
+    input is compared (1e-4 of each input's range), the plant states within the
+    drift those input errors allow (K Ts 1e-4 range on a and delta, and their
+    effect on the rest), and the final warm start in full.  K = 35 crosses
+    several staging chunks of the loop."""
+    from oracle import oracle as O
+    p = W.config2().copy(S=2048, T=30) if not chunk_crossing else W.config2().copy(S=1024, T=20)
+    cid = 416 if not chunk_crossing else 417
+    ctx.set_path(cid, p.path, p.ds)
+    x_cl, u_cl = B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=cid), K)
+    U_warm = B.brmppi_get_nominal(ctx.h, cid, p.T)
+    x = p.x0.astype(np.float64)
+    U = p.u_nom.astype(np.float64)
+    tol = 1e-4 * np.array([4.0, 1.8, p.params["nu_bar"]])
+    worst_u, worst_x = 0.0, 0.0
     for k in range(K):
-        want = O.plant_step(x_cl[k], u_cl[k], p.params)
-        assert np.allclose(x_cl[k + 1], want, rtol=1e-14, atol=1e-14), k
+        o = O.solve(p.copy(seed=p.seed + k), nthreads=16, x0=x, u_nom=U)
+        du = np.abs(u_cl[k] - o["U_new"][0])
+        worst_u = max(worst_u, float((du / tol).max()))
+        assert np.all(du <= tol), (k, du)
+        x = O.plant_step(x, o["U_new"][0], p.params)
+        U = np.concatenate([o["U_new"][1:], o["U_new"][-1:]])
+        dx = np.abs(x_cl[k + 1] - x)
+        worst_x = max(worst_x, float(dx.max()))
+        assert dx.max() <= (k + 1) * p.params["Ts"] * tol.max() * 10.0, (k, dx)
+    log(f"  closed loop K={K}: worst applied-input error {worst_u:.3e} of the tolerance, worst state error {worst_x:.3e}")
+    assert np.all(np.abs(U_warm - U) <= tol)
 
 
 @pytest.mark.parametrize("n_obs,flags,e4", [(7, 0, False), (2, 0, False), (13, W.FLAG_HITCH_OFF, False),
@@ -204,7 +236,7 @@ def test_launch_shapes_bitwise_identical(ctx, n_obs, flags, e4):
     for variant in (0, 1, 2, 3, 4):
         if flags & W.FLAG_GUIDANCE_OFF and variant > 1:
             continue
-        for block in (64, 128, 256):
+        for block in (64, 128, 192, 256):
             log(f"  shape block={block} variant={variant} n_obs={n_obs}")
             B.brmppi_set_launch(ctx.h, block, variant)
             g = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=406), want_J=True, want_useq=True)
@@ -212,6 +244,112 @@ def test_launch_shapes_bitwise_identical(ctx, n_obs, flags, e4):
             assert np.array_equal(g["useq"], ref["useq"]), (block, variant)
             assert np.array_equal(g["U_new"], ref["U_new"]), (block, variant)
     B.brmppi_set_launch(ctx.h, 0, 0)
+
+
+@pytest.mark.parametrize("block,variant", [(192, 0), (192, 2), (192, 3), (96 * 2, 4)])
+def test_block_192_many_groups(ctx, block, variant):
+    """tiles of 192 samples (or 96, 48, 24 with lanes per sample) straddle the
+    groups of 1024 samples: the rollout must leave the reduction to k_reduce,
+    and the update equals the one of block 256, bitwise, over eight groups"""
+    p = W.random_small(85, S=8192, T=10, n_obs=6)
+    ctx.set_path(418, p.path, p.ds)
+    B.brmppi_set_launch(ctx.h, 256, variant)
+    ref = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=418), want_J=True)
+    B.brmppi_set_launch(ctx.h, block, variant)
+    try:
+        g = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=418), want_J=True)
+    finally:
+        B.brmppi_set_launch(ctx.h, 0, 0)
+    assert np.array_equal(g["J"], ref["J"])
+    assert np.array_equal(g["U_new"], ref["U_new"])
+    assert g["stats"]["ess"] == ref["stats"]["ess"]
+
+
+def test_params_null_uses_controller_params(ctx):
+    """a problem without a params pointer runs with its controller's parameters
+    (the library defaults until brmppi_set_params), bitwise as if passed"""
+    p = W.random_small(86, S=1500, T=12, n_obs=4)
+    p = p.copy(params=W.make_params(0.05, dtheta_max=0.5, kappa=0.03, l2=8.0))
+    ctx.set_path(419, p.path, p.ds)
+    want, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=419))
+    B.brmppi_set_params(ctx.h, 419, p.params)
+    got, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(p, controller=419, with_params=False))
+    assert np.array_equal(got, want)
+    # defaults: Ts = 0.05 parameter set of the workloads
+    B.brmppi_set_params(ctx.h, 419, None)
+    q = p.copy(params=W.make_params(0.05))
+    want2, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(q, controller=419))
+    got2, _, _ = B.brmppi_solve(ctx.h, B.ProblemBuffers(q, controller=419, with_params=False))
+    assert np.array_equal(got2, want2)
+    bad = dict(p.params, Ts=-1.0)
+    with pytest.raises(B.BrmppiError) as e:
+        B.brmppi_set_params(ctx.h, 419, bad)
+    assert e.value.code == B.EINVAL
+
+
+def test_closed_loop_reuses_its_buffers(ctx):
+    """a longer closed loop after a shorter one of the same problem allocates
+    nothing: no scratch or pinned staging is re-allocated"""
+    p = W.config2().copy(S=4096, T=40)
+    ctx.set_path(420, p.path, p.ds)
+    B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=420), 5, want_x=False, want_u=False)
+    before = B.brmppi_get_info(ctx.h)
+    B.brmppi_closed_loop(ctx.h, B.ProblemBuffers(p, controller=420), 60, want_x=True, want_u=True)
+    after = B.brmppi_get_info(ctx.h)
+    assert after["scratch_grows"] == before["scratch_grows"]
+    assert after["pinned_grows"] == before["pinned_grows"]
+
+
+def test_served_admission_errors():
+    """EAGAIN once max_inflight requests are queued or unpolled; ETIMEDOUT from
+    a deadline that passes while a request runs, after which the result is
+    still delivered; ENOMEM for a request larger than the arena at submit, and
+    at admission for one that fits the arena's size but can never fit its free
+    space (the context's scratch holds the rest)"""
+    c = B.Context(arena_bytes=96 << 20, n_streams=2, max_controllers=8, max_inflight=2)
+    try:
+        small = W.random_small(87, S=300, T=6, n_obs=2)
+        for k in range(4):
+            c.set_path(k, small.path, small.ds)
+        t1, _ = B.brmppi_submit(c.h, B.ProblemBuffers(small, controller=0))
+        t2, _ = B.brmppi_submit(c.h, B.ProblemBuffers(small, controller=1))
+        _, rc = B.brmppi_submit(c.h, B.ProblemBuffers(small, controller=2), allow=(B.EAGAIN,))
+        assert rc == B.EAGAIN
+        B.brmppi_wait(c.h, t1, small.T)
+        t3, _ = B.brmppi_submit(c.h, B.ProblemBuffers(small, controller=2))   # a slot is free again
+        B.brmppi_wait(c.h, t2, small.T)
+        B.brmppi_wait(c.h, t3, small.T)
+        # ETIMEDOUT: a zero deadline on a request that takes milliseconds
+        big = W.random_small(88, S=32768, T=80, n_obs=20)
+        c.set_path(4, big.path, big.ds)
+        tb, _ = B.brmppi_submit(c.h, B.ProblemBuffers(big, controller=4))
+        _, _, rc = B.brmppi_wait(c.h, tb, big.T, timeout_ms=0, allow=(B.ETIMEDOUT,))
+        assert rc == B.ETIMEDOUT
+        u, st, rc = B.brmppi_wait(c.h, tb, big.T, timeout_ms=60000)
+        assert rc == B.OK and np.all(np.isfinite(u))
+        # ENOMEM at submit: more than the whole arena
+        huge = big.copy(S=1 << 21, T=100)
+        c.set_path(5, huge.path, huge.ds)
+        _, rc = B.brmppi_submit(c.h, B.ProblemBuffers(huge, controller=5), allow=(B.ENOMEM,))
+        assert rc == B.ENOMEM
+        # ENOMEM at admission: a blocking solve leaves a scratch of about half
+        # the arena behind; a request that needs about 60 % of it then never fits
+        mid = big.copy(S=45056, T=100, n_obs=0, obstacles=np.zeros((0, 8), np.float32))
+        c.set_path(6, mid.path, mid.ds)
+        B.brmppi_set_launch(c.h, 128, 0)
+        B.brmppi_solve(c.h, B.ProblemBuffers(mid, controller=6))
+        B.brmppi_set_launch(c.h, 0, 0)
+        info = B.brmppi_get_info(c.h)
+        need = mid.copy(S=60000)
+        c.set_path(7, need.path, need.ds)
+        log(f"  arena used {info['arena_used'] >> 20} MiB of {info['arena_bytes'] >> 20} MiB")
+        tn, rc = B.brmppi_submit(c.h, B.ProblemBuffers(need, controller=7), allow=(B.OK, B.ENOMEM))
+        if rc == B.OK:
+            _, _, rc = B.brmppi_wait(c.h, tn, need.T, timeout_ms=10000, allow=(B.ENOMEM,))
+        assert rc == B.ENOMEM
+        assert B.brmppi_get_info(c.h)["served_failed"] >= 1
+    finally:
+        c.close()
 
 
 def test_default_launch_table_in_effect():

@@ -144,3 +144,31 @@ def test_identity_rollout_follows_nominal(orc):
         s = k * Ts * v0 + Ts**2 * a0 * k * (k - 1) / 2 + Ts**3 * j * k * (k - 1) * (k - 2) / 6
         assert traj[k, 0] == pytest.approx(s, abs=1e-12)
     assert np.isfinite(J)
+
+
+@pytest.mark.parametrize("j,w,nu,j_to,w_to", [
+    (0.7, -0.4, 1.3, None, None),       # inside the box: applied as given
+    (5.0, 0.2, 1.0, "hi", None),        # jerk above its bound
+    (-3.5, 0.2, 1.0, "lo", None),       # jerk below its bound
+    (1.5, 1.5, 1.0, None, "hi"),        # steer rate above its own bound; jerk 1.5 inside +-2 stays
+    (-1.5, -1.2, 1.0, None, "lo"),      # steer rate below its bound
+    (0.3, 0.1, 7.5, None, None),        # progress rate far above nu_bar: never clamped
+    (0.3, 0.1, -4.0, None, None),       # negative progress rate: never clamped
+])
+def test_plant_step_clamps_each_input_to_its_own_bounds(orc, j, w, nu, j_to, w_to):
+    """The closed-loop plant applies U_new[0] with jerk clamped to [j_lo, j_hi]
+    and steer rate to [w_lo, w_hi] (the Sec. V bounds, which differ: +-2 and
+    +-0.9), the progress rate as it is, and steps eq. (6).  The inputs enter the
+    state only through a_{k+1} = a + Ts j, delta_{k+1} = delta + Ts omega and
+    psi_{k+1} = psi + Ts nu (closed forms of the Euler map, checked directly),
+    and the whole step equals the Euler step with the clamped input."""
+    prm = _prm(0.05)
+    ja = {None: j, "hi": prm["j_hi"], "lo": prm["j_lo"]}[j_to]
+    wa = {None: w, "hi": prm["w_hi"], "lo": prm["w_lo"]}[w_to]
+    x = np.array([3.0, -1.0, -1.2, 0.4, 0.3, 0.1, 0.05, 2.0])
+    xn = orc.plant_step(x, [j, w, nu], prm)
+    Ts = prm["Ts"]
+    assert xn[3] == pytest.approx(x[3] + Ts * ja, rel=0, abs=1e-15)
+    assert xn[6] == pytest.approx(x[6] + Ts * wa, rel=0, abs=1e-15)
+    assert xn[7] == pytest.approx(x[7] + Ts * nu, rel=0, abs=1e-15)
+    assert np.array_equal(xn, orc.step(x, [ja, wa, nu], prm))
