@@ -168,6 +168,8 @@ class ProblemBuffers:
         xx = prob.x0 if x0 is None else x0
         for i in range(8):
             c.x0[i] = float(xx[i])
+        if with_nominal and self.u_nom.size < 3 * c.T:
+            raise ValueError(f"nominal sequence holds {self.u_nom.size} floats, the horizon needs {3 * c.T}")
         c.u_nom = _fp(self.u_nom) if with_nominal else None
         c.obs = self.obs
         c.n_obs = int(obs.shape[0])

@@ -328,13 +328,14 @@ def test_served_admission_errors():
         u, st, rc = B.brmppi_wait(c.h, tb, big.T, timeout_ms=60000)
         assert rc == B.OK and np.all(np.isfinite(u))
         # ENOMEM at submit: more than the whole arena
-        huge = big.copy(S=1 << 21, T=100)
+        huge = big.copy(S=1 << 21, T=100, u_nom=np.zeros((100, 3), np.float32))
         c.set_path(5, huge.path, huge.ds)
         _, rc = B.brmppi_submit(c.h, B.ProblemBuffers(huge, controller=5), allow=(B.ENOMEM,))
         assert rc == B.ENOMEM
         # ENOMEM at admission: a blocking solve leaves a scratch of about half
         # the arena behind; a request that needs about 60 % of it then never fits
-        mid = big.copy(S=45056, T=100, n_obs=0, obstacles=np.zeros((0, 8), np.float32))
+        mid = big.copy(S=45056, T=100, u_nom=np.zeros((100, 3), np.float32),
+                       obstacles=np.zeros((0, 8), np.float32))
         c.set_path(6, mid.path, mid.ds)
         B.brmppi_set_launch(c.h, 128, 0)
         B.brmppi_solve(c.h, B.ProblemBuffers(mid, controller=6))
