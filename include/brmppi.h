@@ -58,6 +58,7 @@ extern "C" {
 #define BRMPPI_MAX_S (1u << 22)   /* samples per solve */
 #define BRMPPI_MAX_PATH (1u << 20)/* waypoints per path */
 #define BRMPPI_MAX_BATCH 1024     /* instances per brmppi_solve_batch */
+#define BRMPPI_NOALLOC_MAX_BYTES (64u << 20) /* static scratch of brmppi_solve_noalloc */
 
 /* ---- problem flags ------------------------------------------------------ */
 #define BRMPPI_GUIDANCE_OFF 1u    /* plain MPPI: sampled inputs applied unprojected */
@@ -226,6 +227,23 @@ int brmppi_get_state(brmppi_ctx* ctx, uint32_t controller, double x[8]);
 int brmppi_solve(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st);
 int brmppi_solve_ex(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out,
                     brmppi_stats* st);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): brmppi_solve with its
+ * scratch in a static device array of BRMPPI_NOALLOC_MAX_BYTES (64 MiB) per
+ * GPU, held until the process ends, instead of a block of the arena.  The call
+ * allocates nothing: no arena block, no pinned staging (the 1 MiB buffer made
+ * at create must hold the inputs), no HIP events (profiling flags are ignored).
+ * The controller's path, warm start and plant state stay where brmppi_set_path
+ * put them; results and the warm-start shift equal brmppi_solve's, bitwise.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (the counters a call needs at zero are uploaded with its inputs);
+ * calls of one process on one GPU are serialised, and a call returns only
+ * after its device work is done.  Errors: as brmppi_solve; ENOMEM when the
+ * update needs more scratch than the array holds (about S*T*(3 + 5 + n_obs)*4
+ * bytes) or its inputs more than the staging buffer; ESTATE when the array's
+ * address could not be taken at create. */
+int brmppi_solve_noalloc(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st);
 
 /* ---- batched solve (blocking) ------------------------------------------- */
 /* n independent updates (distinct controllers) together: persistent rollout

@@ -107,6 +107,7 @@ def lib():
         "brmppi_get_state": (I, [ctx, U32, P(D)]),
         "brmppi_solve": (I, [ctx, P(brmppi_problem), P(F), P(brmppi_stats)]),
         "brmppi_solve_ex": (I, [ctx, P(brmppi_problem), P(brmppi_outputs), P(brmppi_stats)]),
+        "brmppi_solve_noalloc": (I, [ctx, P(brmppi_problem), P(F), P(brmppi_stats)]),
         "brmppi_solve_batch": (I, [ctx, P(brmppi_problem), U32, P(P(F)), P(brmppi_stats)]),
         "brmppi_submit": (I, [ctx, P(brmppi_problem), P(U64)]),
         "brmppi_poll": (I, [ctx, U64, P(F), P(brmppi_stats)]),
@@ -232,6 +233,14 @@ def brmppi_solve(ctx, pb: ProblemBuffers, allow=(OK,)):
     u = np.zeros(3 * T, np.float32)
     st = brmppi_stats()
     rc = check(lib().brmppi_solve(ctx, C.byref(pb.c), _fp(u), C.byref(st)), allow)
+    return u.reshape(T, 3), _stats_dict(st), rc
+
+
+def brmppi_solve_noalloc(ctx, pb: ProblemBuffers, allow=(OK,)):
+    T = pb.c.T
+    u = np.zeros(3 * T, np.float32)
+    st = brmppi_stats()
+    rc = check(lib().brmppi_solve_noalloc(ctx, C.byref(pb.c), _fp(u), C.byref(st)), allow)
     return u.reshape(T, 3), _stats_dict(st), rc
 
 

@@ -25,6 +25,8 @@
 
 using namespace brm;
 
+static __device__ __align__(256) char scratch[BRMPPI_NOALLOC_MAX_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -107,6 +109,20 @@ class Arena {
   size_t size_ = 0, used_ = 0;
   std::map<size_t, size_t> free_;
 };
+
+// ---------------------------------------------------------------------------
+// static scratch of brmppi_solve_noalloc
+// ---------------------------------------------------------------------------
+// One array per GPU the library runs on, held until the process ends.  On the
+// host the array's name is only a stand-in for the symbol, never a device
+// address: brmppi_create looks up the array's address on its device with
+// hipGetSymbolAddress (once per device, that device current), and every host
+// use (kernel arguments through the descriptors, copies) goes through that
+// address.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;                        // guards g_static_ptr
+char* g_static_ptr[kMaxDevices] = {};          // the array's address on each device
+std::mutex g_static_call_mu[kMaxDevices];      // one no-alloc call at a time per device
 
 // pinned host staging buffer (allocated at create; re-allocated only when a
 // call needs more, which `grows` counts)
@@ -308,6 +324,10 @@ struct brmppi_ctx {
 
   // blocking-path scratch (cached; re-allocated only when a call needs more)
   Block scratch;
+  // the device's static scratch (brmppi_solve_noalloc), its address on this
+  // context's device
+  char* static_scratch = nullptr;
+  bool no_events = false;       // set while a no-alloc call enqueues: no HIP events are taken
   uint64_t scratch_grows = 0;
   Pinned pin;                   // blocking staging
   hipEvent_t loop_ev[2] = {nullptr, nullptr};   // closed loop: completion of each staging half
@@ -528,8 +548,8 @@ hipEvent_t take_event(brmppi_ctx* ctx) {
 // launch with optional timing (kind: 0 rollout, 1 weights, 2 reduce, 3 plant, 4 noise)
 template <typename F>
 int timed(brmppi_ctx* ctx, hipStream_t st, int kind, F&& launch) {
-  const bool prof = (ctx->flags & BRMPPI_CTX_PROFILE) != 0 ||
-                    ((ctx->flags & BRMPPI_CTX_PROFILE_ROLLOUT) != 0 && (kind == 0 || kind == 4));
+  const bool prof = !ctx->no_events && ((ctx->flags & BRMPPI_CTX_PROFILE) != 0 ||
+                    ((ctx->flags & BRMPPI_CTX_PROFILE_ROLLOUT) != 0 && (kind == 0 || kind == 4)));
   TimedLaunch tl{kind, nullptr, nullptr};
   if (prof) {
     tl.a = take_event(ctx);
@@ -604,7 +624,11 @@ int ensure_scratch(brmppi_ctx* ctx, size_t bytes) {
 // ---------------------------------------------------------------------------
 // plain solve
 // ---------------------------------------------------------------------------
-int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out, brmppi_stats* st) {
+// fixed != nullptr: the scratch is that block of fixed_bytes (the device's
+// static scratch), and the call allocates nothing: no arena block, no pinned
+// staging growth, no HIP events (sizes beyond either are ENOMEM)
+int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs* out, brmppi_stats* st,
+                 char* fixed = nullptr, size_t fixed_bytes = 0) {
   const auto t_start = Clock::now();
   int rc = validate(ctx, p);
   if (rc) return rc;
@@ -616,14 +640,23 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   const size_t lds = fused_lds(*p, sh);
   const InputBlock IB = input_block(p->T, p->u_nom != nullptr, L.n_wchunk);
   const size_t in_off = L.bytes;
-  if ((rc = ensure_scratch(ctx, in_off + round_up(IB.bytes, 256)))) return rc;
-  char* base = ctx->scratch.ptr;
-  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + in_off);
-  hipStream_t s = ctx->streams[0];
-
+  const size_t need = in_off + round_up(IB.bytes, 256);
   const size_t out_floats = 4 + 3 * (size_t)p->T;
   const size_t pin_need = round_up(IB.bytes, 256) + out_floats * sizeof(float);
-  if ((rc = ctx->pin.ensure(pin_need))) return rc;
+  char* base;
+  if (fixed) {
+    if (need > fixed_bytes)
+      return fail(BRMPPI_ENOMEM, "the update needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                     std::to_string(fixed_bytes) + " of the static scratch");
+    if (pin_need > ctx->pin.bytes) return fail(BRMPPI_ENOMEM, "inputs larger than the pinned staging buffer");
+    base = fixed;
+  } else {
+    if ((rc = ensure_scratch(ctx, need))) return rc;
+    if ((rc = ctx->pin.ensure(pin_need))) return rc;
+    base = ctx->scratch.ptr;
+  }
+  SolveDesc* d_desc = reinterpret_cast<SolveDesc*>(base + in_off);
+  hipStream_t s = ctx->streams[0];
   char* pin = ctx->pin.ptr;
   SolveDesc* h_desc = reinterpret_cast<SolveDesc*>(pin);
   float* pin_out = reinterpret_cast<float*>(pin + round_up(IB.bytes, 256));
@@ -634,7 +667,13 @@ int solve_locked(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outputs*
   std::memset(pin + IB.counter, 0, IB.unom - IB.counter);
   if (p->u_nom) std::memcpy(pin + IB.unom, p->u_nom, sizeof(float) * 3 * p->T);
   HIPCHK(hipMemcpyAsync(d_desc, h_desc, IB.bytes, hipMemcpyHostToDevice, s));
-  if ((rc = enqueue_single(ctx, s, d_desc, *p, L, sh, lds))) return rc;
+  ctx->no_events = fixed != nullptr;
+  rc = enqueue_single(ctx, s, d_desc, *p, L, sh, lds);
+  ctx->no_events = false;
+  if (rc) {
+    (void)hipStreamSynchronize(s);   // nothing of this call may still run on the scratch
+    return rc;
+  }
   HIPCHK(hipMemcpyAsync(pin_out, base + L.off_out, out_floats * sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   collect_timing(ctx);
@@ -1371,9 +1410,22 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
     (void)hipGetLastError();
     return fail(BRMPPI_EINVAL, "arena is not device memory");
   }
+  if (cfg->device < 0 || cfg->device >= kMaxDevices) return fail(BRMPPI_EINVAL, "device ordinal out of range");
   HIPCHK(hipSetDevice(cfg->device));
   std::unique_ptr<brmppi_ctx> ctx(new brmppi_ctx());
   ctx->device = cfg->device;
+  {
+    // the static scratch's address on this device (looked up once per device)
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[cfg->device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(BRMPPI_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+      g_static_ptr[cfg->device] = static_cast<char*>(ptr);
+    }
+    ctx->static_scratch = g_static_ptr[cfg->device];
+  }
   ctx->arena.init(cfg->arena, cfg->arena_bytes);
   ctx->n_streams = cfg->n_streams;
   for (uint32_t k = 0; k < cfg->n_streams; ++k) ctx->streams[k] = static_cast<hipStream_t>(cfg->streams[k]);
@@ -1557,6 +1609,17 @@ int brmppi_solve_ex(brmppi_ctx* ctx, const brmppi_problem* p, const brmppi_outpu
 int brmppi_solve(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st) {
   brmppi_outputs o{u_out, nullptr, nullptr};
   return brmppi_solve_ex(ctx, p, &o, st);
+}
+
+int brmppi_solve_noalloc(brmppi_ctx* ctx, const brmppi_problem* p, float* u_out, brmppi_stats* st) {
+  if (!ctx) return fail(BRMPPI_EINVAL, "null context");
+  if (!ctx->static_scratch) return fail(BRMPPI_ESTATE, "no static scratch on this device");
+  std::lock_guard<std::mutex> dev_lk(g_static_call_mu[ctx->device]);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (p && p->controller < ctx->ctrl.size() && ctx->ctrl[p->controller].busy)
+    return fail(BRMPPI_EAGAIN, "controller has a request in flight");
+  brmppi_outputs o{u_out, nullptr, nullptr};
+  return solve_locked(ctx, p, &o, st, ctx->static_scratch, BRMPPI_NOALLOC_MAX_BYTES);
 }
 
 int brmppi_solve_batch(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n, float* const* u_outs,
