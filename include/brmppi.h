@@ -171,8 +171,8 @@ typedef struct {
 } brmppi_outputs;
 
 /* ---- lifecycle ---------------------------------------------------------- */
-/* Create a context over a caller-owned device arena.  Errors: EINVAL (NULL or
- * misaligned arena, n_streams outside 1..4, max_controllers 0), EDEVICE. */
+/* Create a context over a caller-owned device arena.  Errors: EINVAL (NULL
+ * or misaligned arena, n_streams outside 1..4, max_controllers 0), EDEVICE. */
 int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out);
 /* Drain in-flight work, stop the request thread, free host resources.  The
  * arena is the caller's and is not touched afterwards. */

@@ -530,6 +530,28 @@ __device__ __forceinline__ float tracking_cost_sc(const brmppi_params& P, const 
   return P.Qc * ec * ec + P.Ql * el * el + P.Qth1 * e1 * e1 + P.Qth2 * e2 * e2;
 }
 
+// Stage cost r(x, u*, psi) of eq. (13): tracking terms, effort on (j, omega)
+// and the progress term mu (nu_bar - nu)^2.
+__device__ __forceinline__ float stage_cost(const brmppi_params& P, const RefPoint& rf, float sr, float cr, float px,
+                                            float py, float th1, float th2, float uj, float uw, float unu) {
+  const float prog = P.nu_bar - unu;
+  return tracking_cost_sc(P, rf, sr, cr, px, py, th1, th2) + P.R_j * uj * uj + P.R_w * uw * uw +
+         P.mu * prog * prog;
+}
+
+// value held by lane Q of each G-lane group, correct in the group's lane 0
+// (G = 8: lanes 4..7 hold it after a quad permute, and lane 0 reads lane 7
+// through the half-row mirror)
+template <int G, int Q>
+__device__ __forceinline__ float lane_value(float x) {
+  if constexpr (G < 8 || Q < 4) {
+    return group_bcast<G, Q>(x);
+  } else {
+    const float y = group_bcast<4, Q - 4>(x);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), kDppHalfMirror, 0xF, 0xF, true));
+  }
+}
+
 // One sample's rollout over T steps, run by the G lanes of its group (lane g).
 // Rows: every lane computes the hitch row g mod 2 (G = 1: both), obstacle o is
 // computed by lane o mod G in its slot o / G.  After the projection every lane
@@ -588,17 +610,26 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const uint32_t S_pad = d.S_pad;
   float* __restrict__ ustar = d.u_star;
   const float* __restrict__ unom = d.u_nom_in;
-  // The progress rate is not projected, so psi of the next step is known as
-  // soon as a step's inputs are drawn.  With eight lanes per sample (the form
-  // for few samples, where one wave per SIMD leaves every latency exposed) the
-  // next step's reference point (an LDS path lookup) and nominal inputs are
-  // fetched one step ahead, off the dependency chain of the projection and the
-  // state update; the other forms have waves enough to hide them and fewer
-  // registers to spare.  Both orders compute the same values.
+  // With eight lanes per sample (the form for few samples, where one wave per
+  // SIMD leaves every latency exposed) the next step's nominal inputs are
+  // fetched one step ahead, off the dependency chain of the step.
   constexpr bool kAhead = (G == 8);
   constexpr bool kGlb = (G > 1);
-  RefPoint rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  // Stage costs.  One lane per sample evaluates the cost of every step.  With
+  // G > 1 lanes the cost is not repeated on every lane: lane g keeps the cost
+  // inputs of the steps tau with tau % G == g (state, progress and applied
+  // inputs), and once per G steps each lane evaluates the cost of its kept
+  // step, reference lookup included; lane 0 then adds the G costs to J in step
+  // order.  J therefore receives the same terms in the same order as in the
+  // one-lane form, and only lane 0 (the lane that stores) holds it.
+  constexpr bool kBatchCost = (G > 1);
+  RefPoint rf{};
+  if constexpr (!kBatchCost) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  float k_px = 0.0f, k_py = 0.0f, k_th1 = 0.0f, k_th2 = 0.0f, k_psi = 0.0f, k_uj = 0.0f, k_uw = 0.0f, k_unu = 0.0f;
   float un_j = ldf<kGlb>(unom + 0), un_w = ldf<kGlb>(unom + 1), un_nu = ldf<kGlb>(unom + 2);
+  // the hitch rows are owned by lanes 0 and 1; the others zero their copy by
+  // this factor (c = 0 makes every term of the row's sums an exact zero)
+  const float hz_own = (hitch && g < 2) ? 1.0f : 0.0f;
 
   // Precomputed normals are loaded PF = 2 steps ahead into a queue of two
   // slots: step tau reads slot tau % 2 and refills it with step tau + 2.  The
@@ -677,13 +708,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       un_nu = ldf<kGlb>(unom + 3 * tn + 2);
     }
     const float psi_next = psi + Ts * unu;
-    RefPoint rf_next;
-    if constexpr (kAhead) {
-      rf_next = reference<kGlb>(phi0 + psi_next * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
-    } else if (tau > 0) {
-      rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+    if constexpr (!kBatchCost) {
+      if (tau > 0) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     }
-    const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, rf.th1);
+    // (the fourth angle, the reference heading, only for the per-step cost)
+    const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, kBatchCost ? dl : rf.th1);
     const float s1 = tg.s1, c1 = tg.c1, sp = tg.sp, cp = tg.cp;
     const float tn = tg.sd * rcp(tg.cd);    // |delta| stays far from pi/2: cos > 0
     const float kd = tn * inv_l1;     // th1_dot = v kd
@@ -696,8 +725,10 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
 
       // hitch rows, eq. (18) split into h_s = dth_max - kappa v + s (th1 - th2),
       // first-order expansion hhat = h + Ts hd
+      // (with G > 1 lanes the rows are formed whether the instance has them or
+      // not, and zeroed by hz_own: no branch in the step)
       RowTerms H[NH];
-      if (hitch) {
+      if (G > 1 || hitch) {
         const float D = v * inv_l2 * Aw2 - vkd;                 // th2_dot - th1_dot
         const float D_v = inv_l2 * Aw2 - kd;
         const float D_phi = v * inv_l2 * (cp + ch * sp * tn);
@@ -722,14 +753,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
         if constexpr (G == 1) {
           if (hitch && vl < 2) acc_row(A, H[vl]);
         } else if (i == 0) {
-          // lanes 0 and 1 hold the hitch rows; the others add exact zeros
-          // (an accumulator is never -0, so x + 0 keeps its bits)
+          // lanes 0 and 1 hold the hitch rows; the others add exact zeros (c =
+          // 0 and finite g, rr give products of +-0, and an accumulator is
+          // never -0, so x + 0 keeps its bits)
           RowTerms Hz = H[0];
-          const bool own = hitch && vl < 2;
-          Hz.c = sel(own, Hz.c, 0.0f);
-          Hz.g0 = sel(own, Hz.g0, 0.0f);
-          Hz.g1 = sel(own, Hz.g1, 0.0f);
-          Hz.rr = sel(own, Hz.rr, 0.0f);
+          Hz.c *= hz_own;
           acc_row(A, Hz);
         }
 #pragma unroll
@@ -742,18 +770,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
               acc_row(A, O[j]);
             }
           } else if (G * j < n_obs) {
-            // lanes past the last obstacle compute a row from an in-range LDS
-            // slot and contribute zeros, without a divergent branch
+            // lanes past the last obstacle read a staged blank obstacle (Q =
+            // 0): its row has hhat = -1 and Lf = g = +-0, so it adds exact
+            // zeros to the sums, without a divergent branch or selects
             const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
-            RowTerms Rt = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
-            const bool live = o < n_obs;
-            Rt.c = sel(live, Rt.c, 0.0f);
-            Rt.g0 = sel(live, Rt.g0, 0.0f);
-            Rt.g1 = sel(live, Rt.g1, 0.0f);
-            Rt.rr = sel(live, Rt.rr, 0.0f);
-            Rt.Lf = sel(live, Rt.Lf, 0.0f);
-            Rt.ih = sel(live, Rt.ih, 0.0f);
-            O[j] = Rt;
+            O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
             acc_row(A, O[j]);
           }
         }
@@ -765,15 +786,15 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       const double y1 = (double)(P.W_w * uw + pw0) + S8.y1;
       const double det = N00 * N11 - N01 * N01;
       // det > 0 (N is the diagonal W + rho I plus positive semidefinite rank-one
-      // terms): the hardware reciprocal and two Newton steps give 1/det to the
-      // last bits, in 5 instructions instead of the IEEE division's 12
+      // terms): the hardware reciprocal and one Newton step square its relative
+      // error, far below the FP32 rounding of the result (3 instructions
+      // instead of the IEEE division's 12)
       double idet = __builtin_amdgcn_rcp(det);
-      idet = fma(fma(-det, idet, 1.0), idet, idet);
       idet = fma(fma(-det, idet, 1.0), idet, idet);
       uj = (float)((N11 * y0 - N01 * y1) * idet);
       uw = (float)((N00 * y1 - N01 * y0) * idet);
       // next barrier rates: alpha + u*alpha = -(Lf + g u*)/hh (eq. (9) holds exactly)
-      if (hitch) {
+      if (G > 1 || hitch) {
 #pragma unroll
         for (int k = 0; k < NH; ++k) alpha_h[k] = -(H[k].Lf + H[k].g0 * uj + H[k].g1 * uw) * H[k].ih;
       }
@@ -785,11 +806,21 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     }
 
     // --- stage cost r(x_tau, u*_tau, psi_tau), eq. (13) ---
-    const float prog = P.nu_bar - unu;
-    float rc = tracking_cost_sc(P, rf, tg.sr, tg.cr, px, py, th1, th2) + P.R_j * uj * uj +
-               P.R_w * uw * uw + P.mu * prog * prog;
-    if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)tau * Ts);
-    J += (double)rc;
+    if constexpr (!kBatchCost) {
+      float rc = stage_cost(P, rf, tg.sr, tg.cr, px, py, th1, th2, uj, uw, unu);
+      if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)tau * Ts);
+      J += (double)rc;
+    } else {
+      const bool mine = (int)(tau & (G - 1)) == g;
+      k_px = sel(mine, px, k_px);
+      k_py = sel(mine, py, k_py);
+      k_th1 = sel(mine, th1, k_th1);
+      k_th2 = sel(mine, th2, k_th2);
+      k_psi = sel(mine, psi, k_psi);
+      k_uj = sel(mine, uj, k_uj);
+      k_uw = sel(mine, uw, k_uw);
+      k_unu = sel(mine, unu, k_unu);
+    }
 
     // --- applied inputs: [3T][S_pad] in HBM and/or the tile's LDS ---
     if (d.ustar_global && store) {
@@ -814,7 +845,6 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float nth2 = th2 + Ts * v * inv_l2 * Aw2;
     const float ndl = dl + Ts * uw;
     psi = psi_next;
-    if constexpr (kAhead) rf = rf_next;
     px = npx;
     py = npy;
     v = nv;
@@ -823,15 +853,46 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     th2 = nth2;
     dl = ndl;
   };
+  // costs of the kept steps tau0 .. tau0 + n - 1 (lane g: step tau0 + g)
+  auto flush_costs = [&](uint32_t tau0, uint32_t n) __attribute__((always_inline)) {
+    if constexpr (kBatchCost) {
+      const RefPoint r = reference<kGlb>(phi0 + k_psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      float sr, cr;
+      step_sincos(r.th1, &sr, &cr);
+      float rc = stage_cost(P, r, sr, cr, k_px, k_py, k_th1, k_th2, k_uj, k_uw, k_unu);
+      if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, k_px, k_py, t0 + (float)(tau0 + (uint32_t)g) * Ts);
+      J += (double)rc;
+      if (n > 1) J += (double)lane_value<G, 1>(rc);
+      if constexpr (G >= 4) {
+        if (n > 2) J += (double)lane_value<G, 2>(rc);
+        if (n > 3) J += (double)lane_value<G, 3>(rc);
+      }
+      if constexpr (G >= 8) {
+        if (n > 4) J += (double)lane_value<G, 4>(rc);
+        if (n > 5) J += (double)lane_value<G, 5>(rc);
+        if (n > 6) J += (double)lane_value<G, 6>(rc);
+        if (n > 7) J += (double)lane_value<G, 7>(rc);
+      }
+    }
+  };
+  auto after_step = [&](uint32_t tau) __attribute__((always_inline)) {
+    if constexpr (kBatchCost) {
+      if (((tau + 1) & (G - 1)) == 0 || tau + 1 == d.T) flush_costs(tau & ~(uint32_t)(G - 1), (tau & (G - 1)) + 1);
+    }
+  };
   if constexpr (PRE) {
     for (uint32_t tau = 0; tau < d.T; tau += 2) {
       step(tau, std::integral_constant<int, 0>{});
-      if (tau + 1 < d.T) step(tau + 1, std::integral_constant<int, 1>{});
+      after_step(tau);
+      if (tau + 1 < d.T) {
+        step(tau + 1, std::integral_constant<int, 1>{});
+        after_step(tau + 1);
+      }
     }
   } else {
     for (uint32_t tau = 0; tau < d.T; ++tau) step(tau, std::integral_constant<int, 0>{});
   }
-  if constexpr (!kAhead) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
   if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)d.T * Ts);
   J += (double)rN;
@@ -1447,6 +1508,9 @@ void k_rollout(const SolveDesc* __restrict__ descs,
       L.k0 = iax * iax;
       L.k1 = iay * iay;
       s_obs[threadIdx.x] = L;
+    } else if (threadIdx.x < BRMPPI_MAX_OBS) {
+      // blank slots (Q = 0, at rest): the rows of lanes past the last obstacle
+      s_obs[threadIdx.x] = ObsL{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     }
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
       float4 w = d.path[w0 + j];

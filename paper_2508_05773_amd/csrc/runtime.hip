@@ -1456,10 +1456,19 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
   if (!ctx->counters_blk.ptr) return fail(BRMPPI_ENOMEM, "arena too small");
   ctx->counters = reinterpret_cast<BatchCounters*>(ctx->counters_blk.ptr);
   {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->counters), 0u,
-                                   sizeof(BatchCounters) * 5 / 4, ctx->streams[0]);
+    // one staging-sized copy each way before the counters are cleared: the
+    // runtime hands copies above a few KB to a DMA engine whose first use in a
+    // process costs about 8 ms of host time (measured); create pays it
+    // instead of the first call whose upload is that large (a closed loop's
+    // descriptor chunk, a served batch)
+    const size_t cb = std::min(kPinnedInit, cfg->arena_bytes);
+    hipError_t e = hipMemcpyAsync(cfg->arena, ctx->pin.ptr, cb, hipMemcpyHostToDevice, ctx->streams[0]);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->pin.ptr, cfg->arena, cb, hipMemcpyDeviceToHost, ctx->streams[0]);
+    if (e == hipSuccess)
+      e = launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->counters), 0u, sizeof(BatchCounters) * 5 / 4,
+                          ctx->streams[0]);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->streams[0]);
-    if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("counter init: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("context init: ") + hipGetErrorString(e));
   }
   load_tune(ctx.get());
   ctx->running = true;
