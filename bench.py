@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-solves", type=int, default=300)
     ap.add_argument("--served-seconds", type=float, default=0.3, help="simulated seconds of the served leg")
+    ap.add_argument("--served-sweep", default="32,64,96,128,160",
+                    help="controller counts of the served leg's latency sweep below capacity")
+    ap.add_argument("--sweep-seconds", type=float, default=1.0, help="simulated seconds per sweep point")
     ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-extras", action="store_true", help="only the timed closed loop")
     ap.add_argument("--no-cpu", action="store_true")
@@ -382,79 +385,98 @@ def large_leg(B, W, ctx, tune_file):
             "flops_per_launch": fl}
 
 
-def served_leg(args, B, W, ctx):
+def served_replay(args, B, W, ctx, ctrls, n_active, seconds, base_id=300):
+    """Real-time replay of the arrival process of the first n_active controllers
+    (one request per 10 ms tick each, Exp(1 ms) jitter, a random phase), served
+    by continuous batching; every controller runs its closed loop on the device.
+    Returns the solves, the sample-steps and the latency of every request
+    (submit to result ready, the library's clock)."""
     h = ctx.h
-    ctrls = W.config4_controllers()
-    n = len(ctrls)
-    base_id = 300
     pbs = []
-    for c, p in enumerate(ctrls):
+    for c in range(n_active):
+        p = ctrls[c]
         ctx.set_path(base_id + c, p.path, p.ds)
         B.brmppi_set_state(h, base_id + c, p.x0.astype(np.float64))
         flags = B.X0_RESIDENT | B.ADVANCE_PLANT
         pbs.append([B.ProblemBuffers(p, controller=base_id + c, with_nominal=True, flags=flags),
                     B.ProblemBuffers(p, controller=base_id + c, with_nominal=False, flags=flags)])
-    events = W.config4_arrivals(n, args.served_seconds)
-    started = [False] * n
-    outstanding = []          # (ticket, T)
-    lat, done = [], 0
-    t_start = time.perf_counter()
+    events = W.config4_arrivals(n_active, seconds)
+    started = [False] * n_active
+    outstanding = []          # (ticket, T, sample-steps)
+    lat = []
     ss_total = 0
+    t_start = time.perf_counter()
 
-    def drain(block=False):
-        nonlocal done, ss_total
-        while outstanding:
-            t, T, ssk = outstanding[0]
-            if block:
-                u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
-            else:
-                u, st, rc = B.brmppi_poll(h, t, T, allow=(B.OK, B.PENDING, B.ENONFINITE))
-                if rc == B.PENDING:
-                    return
-            outstanding.pop(0)
-            lat.append(st["latency_us"] * 1e-3)
-            done += 1
-            ss_total += ssk
-
-    def outstanding_wait_one():
-        nonlocal done, ss_total
-        t, T, ssk = outstanding.pop(0)
-        u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
+    def take(block):
+        nonlocal ss_total
+        t, T, ssk = outstanding[0]
+        if block:
+            u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
+        else:
+            u, st, rc = B.brmppi_poll(h, t, T, allow=(B.OK, B.PENDING, B.ENONFINITE))
+            if rc == B.PENDING:
+                return False
+        outstanding.pop(0)
         lat.append(st["latency_us"] * 1e-3)
-        done += 1
         ss_total += ssk
+        return True
 
     for (te, c, k) in events:
         while time.perf_counter() - t_start < te:
-            drain()
+            while outstanding and take(False):
+                pass
         pb = pbs[c][1 if started[c] else 0]
         pb.c.seed = (4000 + c * 100003 + k) & (2**64 - 1)
         while True:
             t, rc = B.brmppi_submit(h, pb, allow=(B.OK, B.EAGAIN))
             if rc == B.OK:
                 break
-            # back-pressure: the queue is full, wait for the oldest request
-            outstanding_wait_one()
+            take(True)        # back-pressure: the queue is full, wait for the oldest request
         started[c] = True
         outstanding.append((t, pb.c.T, pb.c.S * pb.c.T))
-        drain()
-    drain(block=True)
+        while outstanding and take(False):
+            pass
+    while outstanding:
+        take(True)
     wall = time.perf_counter() - t_start
+    return events, pbs, lat, ss_total, wall
+
+
+def served_leg(args, B, W, ctx):
+    ctrls = W.config4_controllers()
+    n = len(ctrls)
+    events, pbs, lat, ss_total, wall = served_replay(args, B, W, ctx, ctrls, n, args.served_seconds)
+    done = len(lat)
     # sequential plain solves of the same kind of requests (first 512 events)
     seq_events = events[:512]
     t0 = time.perf_counter()
     for (te, c, k) in seq_events:
-        B.brmppi_solve(h, pbs[c][1], allow=(B.OK, B.ENONFINITE))
+        B.brmppi_solve(ctx.h, pbs[c][1], allow=(B.OK, B.ENONFINITE))
     t_seq = time.perf_counter() - t0
-    return {
+    out = {
         "workload": "256 controllers, S in {2048, 8192, 32768}, T in {30, 50, 100}, 0-32 obstacles "
                     "(10 % moving), one request per 10 ms tick + Exp(1 ms) jitter, closed loop on the device",
         "simulated_s": args.served_seconds, "requests": len(events), "wall_s": wall,
+        "offered_per_s": len(events) / args.served_seconds,
         "solves_per_s": done / wall, "sample_steps_per_s": ss_total / wall,
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
         "sequential_plain_solves_per_s": len(seq_events) / t_seq,
         "speedup_vs_sequential": (done / wall) / (len(seq_events) / t_seq),
     }
+    # latency below capacity: the same mix with fewer controllers (offered load
+    # n x 100 requests/s); the highest load whose p99 stays under the 10 ms tick
+    sweep = []
+    for n_active in [int(x) for x in args.served_sweep.split(",") if x]:
+        ev, _, lt, ss, wl = served_replay(args, B, W, ctx, ctrls, min(n_active, n), args.sweep_seconds)
+        sweep.append({"controllers": min(n_active, n), "offered_per_s": len(ev) / args.sweep_seconds,
+                      "solves_per_s": len(lt) / wl, "p50_ms": pct(lt, 50), "p99_ms": pct(lt, 99),
+                      "max_ms": float(np.max(lt)) if lt else None, "sample_steps_per_s": ss / wl})
+        note(f"served at {sweep[-1]['offered_per_s']:.0f} requests/s: p50 {sweep[-1]['p50_ms']:.2f} ms, "
+             f"p99 {sweep[-1]['p99_ms']:.2f} ms")
+    out["load_sweep"] = sweep
+    ok = [r for r in sweep if r["p99_ms"] is not None and r["p99_ms"] < 10.0]
+    out["max_load_p99_under_tick"] = max(ok, key=lambda r: r["offered_per_s"]) if ok else None
+    return out
 
 
 def host_cpu():

@@ -53,7 +53,8 @@ extern "C" {
                                      request was admitted */
 
 /* ---- limits ------------------------------------------------------------- */
-#define BRMPPI_MAX_OBS 32         /* obstacles per solve */
+#define BRMPPI_MAX_OBS 32         /* obstacle rows per solve: obstacles x footprint discs */
+#define BRMPPI_MAX_DISCS 4        /* footprint discs per body (tractor, trailer) */
 #define BRMPPI_MAX_T 512          /* horizon */
 #define BRMPPI_MAX_S (1u << 22)   /* samples per solve */
 #define BRMPPI_MAX_PATH (1u << 20)/* waypoints per path */
@@ -117,7 +118,18 @@ typedef struct {
  *  baseline (Sec. V):         w_col, weight of the collision penalty added to the
  *                              stage and terminal costs under BRMPPI_COLLISION_PENALTY
  *  stabiliser, eq. (19):      qh_j, qh_w (diagonal Q_h), alpha_h (class-K rate of the
- *                              hitch rows) of the CBF-QP under BRMPPI_HITCH_QP */
+ *                              hitch rows) of the CBF-QP under BRMPPI_HITCH_QP
+ *  footprint, Sec. IV-C:      discs of radius r_disc covering the vehicle: disc_tractor[k]
+ *                              (k < n_disc_tractor) metres ahead of the tractor's rear
+ *                              axle along its heading, disc_trailer[k] (k < n_disc_trailer)
+ *                              metres behind the hitch along the trailer's heading (the
+ *                              hitch sits lh behind the rear axle).  Every (disc, obstacle)
+ *                              pair is one barrier row, disc by disc (tractor discs first),
+ *                              obstacles in order; eq. (17) expands each around its disc
+ *                              centre along the drift (inputs zero).  1..4 discs per body
+ *                              counted together at least 1; n_obs times the disc count at
+ *                              most BRMPPI_MAX_OBS.  The defaults are one disc at the rear
+ *                              axle, the point eq. (16) uses. */
 typedef struct {
   float Ts, l1, lh, l2, dtheta_max, kappa, r_disc;
   float Qc, Ql, Qth1, Qth2, R_j, R_w, mu, nu_bar;
@@ -126,6 +138,8 @@ typedef struct {
   float h_eps;
   float w_col;   /* weight of the collision-penalty baseline (BRMPPI_COLLISION_PENALTY) */
   float qh_j, qh_w, alpha_h;  /* hitch-angle stabiliser (BRMPPI_HITCH_QP): Q_h, class-K rate */
+  float disc_tractor[BRMPPI_MAX_DISCS], disc_trailer[BRMPPI_MAX_DISCS];
+  uint32_t n_disc_tractor, n_disc_trailer;
 } brmppi_params;
 
 /* Obstacle (Sec. IV-C, eq. (16)): centre (cx, cy) at t = 0, semi-axes (mx, my),
@@ -143,7 +157,7 @@ typedef struct {
   const float* u_nom;         /* T*3 nominal sequence, or NULL = the controller's resident
                                  warm start (the shifted result of its last update) */
   const brmppi_obstacle* obs; /* n_obs records */
-  uint32_t n_obs;             /* 0..BRMPPI_MAX_OBS */
+  uint32_t n_obs;             /* 0..BRMPPI_MAX_OBS, and n_obs x footprint discs <= BRMPPI_MAX_OBS */
   float t0;                   /* time of x0 for moving obstacles */
   float lambda;               /* temperature of the weights, > 0 */
   uint64_t seed;              /* Philox key */
@@ -155,6 +169,9 @@ typedef struct {
                                  brmppi_default_params until set) */
 } brmppi_problem;
 
+/* Statistics of one update.  (Every barrier row takes part in the projection
+ * at every step -- no row is switched off by a buffer zone -- so a fraction of
+ * active rows would be 1 by construction and is not reported.) */
 typedef struct {
   float J_min;                /* min_s J_s */
   float Z;                    /* sum_s exp(-(J_s - J_min)/lambda) */

@@ -139,24 +139,84 @@ static double ipow(double y, int k) {
   return r;
 }
 
-void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, const orc_params* p,
-                          orc_barrier* out) {
-  const double v = x[2], a = x[3], th1 = x[4], dl = x[6];
+/* Footprint disc (Sec. IV-C: the vehicle body covered by discs of radius r).
+ * READING: a disc centre is c = p + A e1 - B f2, with p the tractor's rear
+ * axle, e1 = (cos th1, sin th1) and f2 = (cos th2, sin th2): a tractor disc a
+ * metres ahead of the rear axle has (A, B) = (a, 0); a trailer disc b metres
+ * behind the hitch, which sits lh behind the rear axle (the hitch geometry of
+ * eq. (6)), has (A, B) = (-lh, b).  (0, 0) is the rear axle itself, the point
+ * eq. (16) uses.  Along the drift (inputs zero) the centre moves with
+ *   c'   = v e1 + A w1 e2 - B w2 n2,
+ *   c''  = a e1 + v w1 e2 + A (w1' e2 - w1^2 e1) - B (w2' n2 - w2^2 f2),
+ * e2, n2 the left normals of e1, f2, w1 = th1' = v tan(delta)/l1 and
+ * w2 = th2' = v W(phi, delta) from eq. (6), phi = th1 - th2, and along the
+ * drift w1' = a tan(delta)/l1, w2' = a W + v W_phi (w1 - w2). */
+typedef struct {
+  double c[2], cd[2], cdd[2];            /* centre, velocity, drift acceleration */
+  double J0[8][2], J1[8][2], J2[8][2];   /* their partials in the 8 states */
+} orc_disc_kin;
+
+static void disc_kinematics(const double x[8], double A, double B, const orc_params* p, orc_disc_kin* k) {
+  const double v = x[2], a = x[3], th1 = x[4], th2 = x[5], dl = x[6];
+  const double e1[2] = {cos(th1), sin(th1)}, e2[2] = {-sin(th1), cos(th1)};
+  const double f2[2] = {cos(th2), sin(th2)}, n2[2] = {-sin(th2), cos(th2)};
+  const double tn = tan(dl), sec2 = 1.0 + tn * tn, ch = p->lh / p->l1, phi = th1 - th2;
+  const double kd = tn / p->l1, dkd = sec2 / p->l1;
+  const double W = (sin(phi) - ch * cos(phi) * tn) / p->l2;
+  const double Wp = (cos(phi) + ch * sin(phi) * tn) / p->l2;     /* dW/dphi (and d^2W/dphi^2 = -W) */
+  const double Wd = -ch * cos(phi) * sec2 / p->l2;              /* dW/d delta */
+  const double Wpd = ch * sin(phi) * sec2 / p->l2;              /* d^2W/dphi d delta */
+  const double w1 = v * kd, w2 = v * W;
+  const double w1d = a * kd;                                    /* w1' along the drift */
+  const double w2d = a * W + v * Wp * (w1 - w2);                /* w2' along the drift */
+  memset(k, 0, sizeof(*k));
+  for (int i = 0; i < 2; ++i) {
+    k->c[i] = x[i] + A * e1[i] - B * f2[i];
+    k->cd[i] = v * e1[i] + A * w1 * e2[i] - B * w2 * n2[i];
+    k->cdd[i] = a * e1[i] + v * w1 * e2[i] + A * (w1d * e2[i] - w1 * w1 * e1[i]) - B * (w2d * n2[i] - w2 * w2 * f2[i]);
+  }
+  /* partials of w1, w1', w2, w2' in v, th1, th2, delta (a: w1' and w2' only) */
+  const double w2d_v = Wp * (w1 - w2) + v * Wp * (kd - W);
+  const double w2d_th1 = a * Wp - v * W * (w1 - w2) - v * v * Wp * Wp;
+  const double w2d_dl = a * Wd + v * Wpd * (w1 - w2) + v * Wp * (v * dkd - v * Wd);
+  for (int i = 0; i < 2; ++i) {
+    /* position: p, th1 (e1), th2 (f2) */
+    k->J0[0][i] = (i == 0);
+    k->J0[1][i] = (i == 1);
+    k->J0[4][i] = A * e2[i];
+    k->J0[5][i] = -B * n2[i];
+    /* velocity */
+    k->J1[2][i] = e1[i] + A * kd * e2[i] - B * W * n2[i];
+    k->J1[4][i] = v * e2[i] - A * w1 * e1[i] - B * v * Wp * n2[i];
+    k->J1[5][i] = B * v * Wp * n2[i] + B * w2 * f2[i];
+    k->J1[6][i] = A * v * dkd * e2[i] - B * v * Wd * n2[i];
+    /* drift acceleration */
+    k->J2[2][i] = 2.0 * w1 * e2[i] - 2.0 * A * w1 * kd * e1[i] - B * (w2d_v * n2[i] - 2.0 * w2 * W * f2[i]);
+    k->J2[3][i] = e1[i] + A * kd * e2[i] - B * W * n2[i];
+    k->J2[4][i] = a * e2[i] - v * w1 * e1[i] + A * (-w1d * e1[i] - w1 * w1 * e2[i]) -
+                  B * (w2d_th1 * n2[i] - 2.0 * w2 * v * Wp * f2[i]);
+    k->J2[5][i] = -B * (-w2d_th1 * n2[i] - w2d * f2[i] + 2.0 * w2 * v * Wp * f2[i] - w2 * w2 * n2[i]);
+    k->J2[6][i] = v * v * dkd * e2[i] + A * (a * dkd * e2[i] - 2.0 * w1 * v * dkd * e1[i]) -
+                  B * (w2d_dl * n2[i] - 2.0 * w2 * v * Wd * f2[i]);
+  }
+}
+
+/* the barrier of eqs. (16)-(17) for obstacle o around the disc centre (A, B) */
+void orc_disc_barrier(const double x[8], double t, const orc_obstacle* o, double A, double B,
+                      const orc_params* p, orc_barrier* out) {
   const double Ts = p->Ts;
   const int e = (int)o->e;
   const double co = cos(o->heading), so = sin(o->heading);
   const double R[2][2] = {{co, so}, {-so, co}};          /* world -> obstacle frame */
   const double rho[2] = {1.0 / (o->mx + p->r_disc), 1.0 / (o->my + p->r_disc)};
+  orc_disc_kin K;
+  disc_kinematics(x, A, B, p, &K);
 
   const double vo[2] = {o->vx, o->vy};
-  const double d[2] = {x[0] - (o->cx + o->vx * t), x[1] - (o->cy + o->vy * t)};
-  const double e1[2] = {cos(th1), sin(th1)};
-  const double e2[2] = {-sin(th1), cos(th1)};
-  const double kd = tan(dl) / p->l1;           /* curvature: th1_dot = v kd */
-  const double dkd = (1.0 + tan(dl) * tan(dl)) / p->l1;
-  /* d_dot and d_ddot along the drift */
-  const double dd[2] = {v * e1[0] - vo[0], v * e1[1] - vo[1]};
-  const double ddd[2] = {a * e1[0] + v * v * kd * e2[0], a * e1[1] + v * v * kd * e2[1]};
+  const double d[2] = {K.c[0] - (o->cx + o->vx * t), K.c[1] - (o->cy + o->vy * t)};
+  /* d_dot and d_ddot along the drift (the obstacle moves at constant velocity) */
+  const double dd[2] = {K.cd[0] - vo[0], K.cd[1] - vo[1]};
+  const double* ddd = K.cdd;
 
   /* per-axis derivatives of phi in the obstacle frame */
   double dp[2], f0 = -1.0, f1[2], f2[2], f3[2];
@@ -190,35 +250,41 @@ void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, co
   out->hdd = hdd;
   out->hhat = h + Ts * hd + 0.5 * Ts * Ts * hdd;
 
-  /* partial derivatives of h, hd, hdd (chain rule, term by term) */
-  double gh[8] = {0}, ghd[8] = {0}, ghdd[8] = {0};
-  double th, thd, thdd; /* time partials */
-  /* h(d) */
-  gh[0] = G[0];
-  gh[1] = G[1];
-  th = -dot2(vo, G);
-  /* hd = G(d) . dd;  dd depends on v, th1 */
-  ghd[0] = Hdd[0];
-  ghd[1] = Hdd[1];
-  ghd[2] = dot2(G, e1);                        /* d dd / dv = e1 */
-  ghd[4] = v * dot2(G, e2);                    /* d dd / dth1 = v e2 */
-  thd = -dot2(vo, Hdd);
-  /* hdd = dd' H(d) dd + G(d) . ddd;  ddd depends on v, a, th1, delta */
-  ghdd[0] = T3dd[0] + Hddd[0];
-  ghdd[1] = T3dd[1] + Hddd[1];
-  {
-    const double dddv[2] = {2.0 * v * kd * e2[0], 2.0 * v * kd * e2[1]};
-    const double dddth[2] = {a * e2[0] - v * v * kd * e1[0], a * e2[1] - v * v * kd * e1[1]};
-    const double ddddl[2] = {v * v * dkd * e2[0], v * v * dkd * e2[1]};
-    ghdd[2] = 2.0 * dot2(e1, Hdd) + dot2(G, dddv);
-    ghdd[3] = dot2(G, e1);
-    ghdd[4] = 2.0 * v * dot2(e2, Hdd) + dot2(G, dddth);
-    ghdd[6] = dot2(G, ddddl);
+  /* partial derivatives of h, hd, hdd (chain rule through c, c', c'') */
+  for (int i = 0; i < 8; ++i) {
+    const double* j0 = K.J0[i];
+    const double* j1 = K.J1[i];
+    const double* j2 = K.J2[i];
+    double Hj0[2];
+    mat2_vec(H, j0, Hj0);
+    const double gh = dot2(G, j0);
+    const double ghd = dot2(dd, Hj0) + dot2(G, j1);
+    const double ghdd = dot2(T3dd, j0) + 2.0 * dot2(Hdd, j1) + dot2(ddd, Hj0) + dot2(G, j2);
+    out->grad[i] = gh + Ts * ghd + 0.5 * Ts * Ts * ghdd;
   }
-  thdd = -(T3dd[0] * vo[0] + T3dd[1] * vo[1]) - dot2(vo, Hddd);
-
-  for (int i = 0; i < 8; ++i) out->grad[i] = gh[i] + Ts * ghd[i] + 0.5 * Ts * Ts * ghdd[i];
+  /* time partials: d depends on t through -v_o t */
+  const double th = -dot2(vo, G);
+  const double thd = -dot2(vo, Hdd);
+  const double thdd = -(T3dd[0] * vo[0] + T3dd[1] * vo[1]) - dot2(vo, Hddd);
   out->dt = th + Ts * thd + 0.5 * Ts * Ts * thdd;
+}
+
+/* eq. (16) as printed: the rear axle's point */
+void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, const orc_params* p,
+                          orc_barrier* out) {
+  orc_disc_barrier(x, t, o, 0.0, 0.0, p, out);
+}
+
+/* disc k of the footprint in row order: the tractor's, then the trailer's */
+int orc_num_discs(const orc_params* p) { return p->n_disc_tractor + p->n_disc_trailer; }
+void orc_disc(const orc_params* p, int k, double* A, double* B) {
+  if (k < p->n_disc_tractor) {
+    *A = p->disc_tractor[k];
+    *B = 0.0;
+  } else {
+    *A = -p->lh;
+    *B = p->disc_trailer[k - p->n_disc_tractor];
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -274,19 +340,20 @@ void orc_hitch_barrier(const double x[8], int sign, const orc_params* p, orc_bar
 /*   Lf_i = Ts (grad hhat . f_c + d hhat/dt)   (f = Ts f_c, Sec. III-A)      */
 /*   g_i  = Ts (d hhat/da, d hhat/d delta)     (jerk, steer-rate columns;     */
 /*          the progress-rate column is zero because hhat does not involve psi)*/
-/* Order: hitch (+), hitch (-) (absent with ORC_HITCH_OFF), then the          */
-/* obstacles as given.                                                        */
+/* Order: hitch (+), hitch (-) (absent with ORC_HITCH_OFF), then one row per */
+/* (footprint disc, obstacle), disc by disc (orc_disc), obstacles as given.  */
 /* READING (guard against a singular A M^-1 A'): hhat is replaced by           */
 /* copysign(max(|hhat|, h_eps), hhat), with 0 mapped to +h_eps.                */
 /* ------------------------------------------------------------------------ */
-int orc_num_rows(const orc_problem* pr) {
-  return pr->n_obs + ((pr->flags & ORC_HITCH_OFF) ? 0 : 2);
+int orc_num_rows(const orc_problem* pr, const orc_params* p) {
+  return pr->n_obs * orc_num_discs(p) + ((pr->flags & ORC_HITCH_OFF) ? 0 : 2);
 }
 
 /* Normals drawn per (sample, step): 0..2 perturb (j, omega, nu); 3 and 4 are
- * the auxiliary inputs of the hitch rows (+, -); 5 + o that of obstacle o.
- * The numbering does not depend on ORC_HITCH_OFF (3 and 4 are then unused). */
-int orc_num_normals(const orc_problem* pr) { return 5 + pr->n_obs; }
+ * the auxiliary inputs of the hitch rows (+, -); 5 + k n_obs + o that of the
+ * row of disc k and obstacle o.  The numbering does not depend on
+ * ORC_HITCH_OFF (3 and 4 are then unused). */
+int orc_num_normals(const orc_problem* pr, const orc_params* p) { return 5 + pr->n_obs * orc_num_discs(p); }
 
 /* normal index of row i in the order produced by orc_rows */
 static int row_normal(const orc_problem* pr, int i) {
@@ -319,10 +386,14 @@ void orc_rows(const orc_problem* pr, const orc_params* p, const double x[8], dou
       row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
     }
   }
-  for (int o = 0; o < pr->n_obs; ++o, ++i) {
-    orc_barrier B;
-    orc_obstacle_barrier(x, t, &pr->obs[o], p, &B);
-    row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
+  for (int k = 0; k < orc_num_discs(p); ++k) {
+    double A, Bd;
+    orc_disc(p, k, &A, &Bd);
+    for (int o = 0; o < pr->n_obs; ++o, ++i) {
+      orc_barrier B;
+      orc_disc_barrier(x, t, &pr->obs[o], A, Bd, p, &B);
+      row_from_barrier(&B, f, p, &hraw[i], &hh[i], &G[2 * i], &Lf[i]);
+    }
   }
 }
 
@@ -465,12 +536,17 @@ double orc_stage_cost(const double x[8], const double u[3], const double* path, 
 /* the obstacle function of eq. (16) (exponent e = 2 or 4, as the obstacle   */
 /* has it) at the current state and time, added to the stage cost of every   */
 /* step and to the terminal cost.                                            */
+/* With several footprint discs every (disc, obstacle) pair is penalised.     */
 double orc_collision_penalty(const double x[8], double t, const orc_obstacle* obs, int n_obs, const orc_params* p) {
   double pen = 0.0;
-  for (int o = 0; o < n_obs; ++o) {
-    orc_barrier B;
-    orc_obstacle_barrier(x, t, &obs[o], p, &B);
-    if (B.h < 0.0) pen += B.h * B.h;
+  for (int k = 0; k < orc_num_discs(p); ++k) {
+    double A, Bd;
+    orc_disc(p, k, &A, &Bd);
+    for (int o = 0; o < n_obs; ++o) {
+      orc_barrier B;
+      orc_disc_barrier(x, t, &obs[o], A, Bd, p, &B);
+      if (B.h < 0.0) pen += B.h * B.h;
+    }
   }
   return p->w_col * pen;
 }
@@ -493,8 +569,8 @@ double orc_terminal_cost(const double x[8], const double* path, int n, double ds
 /* ------------------------------------------------------------------------ */
 double orc_rollout(const orc_problem* pr, const orc_params* p, uint32_t s, const double* eps,
                    double* useq, double* traj, double* alphas) {
-  const int nc = orc_num_rows(pr);
-  const int K = orc_num_normals(pr);
+  const int nc = orc_num_rows(pr, p);
+  const int K = orc_num_normals(pr, p);
   const int guided = !(pr->flags & ORC_GUIDANCE_OFF);
   double x[8];
   memcpy(x, pr->x0, sizeof(x));
@@ -589,7 +665,7 @@ int orc_weights(const double* J, int S, double lambda, double* wbar, double* m_o
 int orc_solve(const orc_problem* pr, const orc_params* p, int nthreads, const double* eps,
               double* U_new, double* J, double* wbar, double* useq_all, double* stats) {
   const int S = pr->S, T = pr->T;
-  const int K = orc_num_normals(pr);
+  const int K = orc_num_normals(pr, p);
   int own = 0;
   if (!useq_all) {
     useq_all = (double*)malloc(sizeof(double) * (size_t)S * T * 3);

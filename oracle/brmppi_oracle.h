@@ -24,6 +24,10 @@ typedef struct {
   double h_eps;
   double w_col;                /* collision-penalty weight (baseline flag only) */
   double qh_j, qh_w, alpha_h;  /* hitch-angle stabiliser QP, eq. (19): Q_h, class-K rate */
+  /* footprint discs (Sec. IV-C): tractor discs a metres ahead of the rear axle,
+   * trailer discs b metres behind the hitch; one barrier row per (disc, obstacle) */
+  double disc_tractor[4], disc_trailer[4];
+  int n_disc_tractor, n_disc_trailer;
 } orc_params;
 
 /* obstacle: centre, semi-axes, orientation, exponent, constant velocity */
@@ -63,9 +67,13 @@ void orc_step(const double x[8], const double u[3], const orc_params* p, double 
 void orc_obstacle_barrier(const double x[8], double t, const orc_obstacle* o, const orc_params* p,
                           orc_barrier* out);
 void orc_hitch_barrier(const double x[8], int sign, const orc_params* p, orc_barrier* out);
+void orc_disc_barrier(const double x[8], double t, const orc_obstacle* o, double A, double B,
+                      const orc_params* p, orc_barrier* out);
+int orc_num_discs(const orc_params* p);
+void orc_disc(const orc_params* p, int k, double* A, double* B);
 
-int orc_num_rows(const orc_problem* pr);
-int orc_num_normals(const orc_problem* pr);
+int orc_num_rows(const orc_problem* pr, const orc_params* p);
+int orc_num_normals(const orc_problem* pr, const orc_params* p);
 void orc_rows(const orc_problem* pr, const orc_params* p, const double x[8], double t,
               double* hraw, double* hh, double* G, double* Lf);
 

@@ -30,7 +30,9 @@ HITCH_QP = 32
 
 
 class Params(C.Structure):
-    _fields_ = [(k, C.c_double) for k in PARAM_FIELDS]
+    _fields_ = [(k, C.c_double) for k in PARAM_FIELDS] + [
+        ("disc_tractor", C.c_double * 4), ("disc_trailer", C.c_double * 4),
+        ("n_disc_tractor", C.c_int), ("n_disc_trailer", C.c_int)]
 
 
 class Obstacle(C.Structure):
@@ -79,10 +81,14 @@ def lib():
         L.orc_step.argtypes = [P, P, C.POINTER(Params), P]
         L.orc_obstacle_barrier.argtypes = [P, D, C.POINTER(Obstacle), C.POINTER(Params), C.POINTER(Barrier)]
         L.orc_hitch_barrier.argtypes = [P, I, C.POINTER(Params), C.POINTER(Barrier)]
-        L.orc_num_rows.argtypes = [C.POINTER(ProblemC)]
+        L.orc_num_rows.argtypes = [C.POINTER(ProblemC), C.POINTER(Params)]
         L.orc_num_rows.restype = I
-        L.orc_num_normals.argtypes = [C.POINTER(ProblemC)]
+        L.orc_num_normals.argtypes = [C.POINTER(ProblemC), C.POINTER(Params)]
         L.orc_num_normals.restype = I
+        L.orc_disc_barrier.argtypes = [P, D, C.POINTER(Obstacle), D, D, C.POINTER(Params), C.POINTER(Barrier)]
+        L.orc_num_discs.argtypes = [C.POINTER(Params)]
+        L.orc_num_discs.restype = I
+        L.orc_disc.argtypes = [C.POINTER(Params), I, P, P]
         L.orc_rows.argtypes = [C.POINTER(ProblemC), C.POINTER(Params), P, D, P, P, P, P]
         L.orc_project.argtypes = [I, P, P, P, P, P, C.POINTER(Params), P]
         L.orc_project.restype = I
@@ -115,7 +121,15 @@ def _dp(a):
 
 
 def params_struct(p: dict) -> Params:
-    return Params(**{k: float(p[k]) for k in PARAM_FIELDS})
+    P = Params(**{k: float(p[k]) for k in PARAM_FIELDS})
+    dt, dr = list(p.get("disc_tractor", [0.0])), list(p.get("disc_trailer", []))
+    assert len(dt) <= 4 and len(dr) <= 4
+    for i, v in enumerate(dt):
+        P.disc_tractor[i] = float(v)
+    for i, v in enumerate(dr):
+        P.disc_trailer[i] = float(v)
+    P.n_disc_tractor, P.n_disc_trailer = len(dt), len(dr)
+    return P
 
 
 def obstacle_struct(o) -> Obstacle:
@@ -152,11 +166,11 @@ class OracleProblem:
 
     @property
     def n_c(self):
-        return lib().orc_num_rows(C.byref(self.c))
+        return lib().orc_num_rows(C.byref(self.c), C.byref(self.params))
 
     @property
     def n_normals(self):
-        return lib().orc_num_normals(C.byref(self.c))
+        return lib().orc_num_normals(C.byref(self.c), C.byref(self.params))
 
 
 def solve(prob, nthreads=None, eps=None, want_useq=False, **kw):
@@ -264,6 +278,27 @@ def obstacle_barrier(x, t, obs, params):
     O = obstacle_struct(obs)
     lib().orc_obstacle_barrier(_dp(x), float(t), C.byref(O), C.byref(P), C.byref(B))
     return dict(h=B.h, hd=B.hd, hdd=B.hdd, hhat=B.hhat, grad=np.array(B.grad[:]), dt=B.dt)
+
+
+def disc_barrier(x, t, obs, A, B, params):
+    """the obstacle barrier around the footprint disc centre p + A e1 - B f2"""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    Bo = Barrier()
+    P = params_struct(params)
+    O = obstacle_struct(obs)
+    lib().orc_disc_barrier(_dp(x), float(t), C.byref(O), float(A), float(B), C.byref(P), C.byref(Bo))
+    return dict(h=Bo.h, hd=Bo.hd, hdd=Bo.hdd, hhat=Bo.hhat, grad=np.array(Bo.grad[:]), dt=Bo.dt)
+
+
+def discs(params):
+    """(A, B) of every footprint disc in row order"""
+    P = params_struct(params)
+    out = []
+    for k in range(lib().orc_num_discs(C.byref(P))):
+        A, B = C.c_double(), C.c_double()
+        lib().orc_disc(C.byref(P), k, C.byref(A), C.byref(B))
+        out.append((A.value, B.value))
+    return out
 
 
 def hitch_barrier(x, sign, params):

@@ -46,8 +46,13 @@ class brmppi_config(C.Structure):
                 ("autotune_cache", C.c_char_p), ("flags", C.c_uint32), ("device", C.c_int32)]
 
 
+MAX_DISCS = 4
+
+
 class brmppi_params(C.Structure):
-    _fields_ = [(k, C.c_float) for k in PARAM_FIELDS]
+    _fields_ = [(k, C.c_float) for k in PARAM_FIELDS] + [
+        ("disc_tractor", C.c_float * MAX_DISCS), ("disc_trailer", C.c_float * MAX_DISCS),
+        ("n_disc_tractor", C.c_uint32), ("n_disc_trailer", C.c_uint32)]
 
 
 class brmppi_obstacle(C.Structure):
@@ -151,7 +156,16 @@ def _dp(a):
 
 
 def params_struct(p: dict) -> brmppi_params:
-    return brmppi_params(**{k: float(p[k]) for k in PARAM_FIELDS})
+    P = brmppi_params(**{k: float(p[k]) for k in PARAM_FIELDS})
+    dt, dr = list(p.get("disc_tractor", [0.0])), list(p.get("disc_trailer", []))
+    if len(dt) > MAX_DISCS or len(dr) > MAX_DISCS:
+        raise ValueError("at most 4 footprint discs per body")
+    for i, v in enumerate(dt):
+        P.disc_tractor[i] = float(v)
+    for i, v in enumerate(dr):
+        P.disc_trailer[i] = float(v)
+    P.n_disc_tractor, P.n_disc_trailer = len(dt), len(dr)
+    return P
 
 
 class ProblemBuffers:
@@ -353,7 +367,10 @@ def brmppi_get_info(ctx) -> dict:
 def brmppi_default_params() -> dict:
     p = brmppi_params()
     check(lib().brmppi_default_params(C.byref(p)))
-    return {k: float(getattr(p, k)) for k in PARAM_FIELDS}
+    out = {k: float(getattr(p, k)) for k in PARAM_FIELDS}
+    out["disc_tractor"] = [float(p.disc_tractor[i]) for i in range(p.n_disc_tractor)]
+    out["disc_trailer"] = [float(p.disc_trailer[i]) for i in range(p.n_disc_trailer)]
+    return out
 
 
 def brmppi_set_params(ctx, controller, params):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbrmppi.so")
 SOURCES = ["kernels.hip", "runtime.hip"]
-HEADERS = ["brmppi_internal.h"]
+HEADERS = ["brmppi_internal.h", "served_core.h"]
 
 ARCH = os.environ.get("BRMPPI_ARCH", "gfx950")
 
@@ -56,7 +56,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(o)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread",
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -30,12 +30,15 @@ struct alignas(16) SolveDesc {
   float inv_lambda;
   float x0[8];                  // px, py, v, a, th1, th2, delta, psi
   float t0, lambda, ds, inv_ds;
-  uint32_t S, T, n_obs, flags;
+  uint32_t S, T, n_obs, flags;  // n_obs: obstacle rows (obstacles x footprint discs)
   uint32_t n_path, instance, seed_lo, seed_hi;
   uint32_t S_pad, n_wchunk, n_rgroup, n_ritems;
   uint32_t x0_resident, n_normals, fused, ustar_global;   // n_normals: 5 + n_obs (guided) or 3
-  uint32_t n_units, any_e4, rows_item, pad3;   // any_e4: some obstacle has e = 4; rows_item: rows
-                                               // of one reduce work item
+  uint32_t n_units, any_e4, rows_item, any_disc;   // any_e4: some obstacle has e = 4; rows_item: rows
+                                                   // of one reduce work item; any_disc: a footprint
+                                                   // other than the rear axle alone
+  uint32_t n_objects, pad0, pad1, pad2;          // obstacles (row r: obstacle r % n_objects, disc
+                                                 // r / n_objects)
   const float4* path;           // controller path (absolute coordinates)
   const float* u_nom_in;        // 3T nominal sequence read by the rollout
   float* u_nom_out;             // 3T warm-start slot of the controller (shift target)
@@ -108,7 +111,25 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st
 // occupancy of a rollout variant for a bucket and block size (blocks per CU)
 int rollout_blocks_per_cu(int bucket, int variant, uint32_t block);
 
-// constraint bucket: obstacles the kernel instance can hold (0 = guidance off)
+// footprint discs of a parameter set, and whether it is other than the rear
+// axle alone (the point eq. (16) uses)
+inline uint32_t n_discs(const brmppi_params& P) { return P.n_disc_tractor + P.n_disc_trailer; }
+inline bool footprint_is_rear_axle(const brmppi_params& P) {
+  return P.n_disc_tractor == 1 && P.n_disc_trailer == 0 && P.disc_tractor[0] == 0.0f;
+}
+// (A, B) of disc k in row order: centre p + A e1 - B f2 (tractor discs ahead of
+// the rear axle, then trailer discs behind the hitch, lh behind the rear axle)
+__host__ __device__ inline void disc_ab(const brmppi_params& P, uint32_t k, float& A, float& B) {
+  if (k < P.n_disc_tractor) {
+    A = P.disc_tractor[k];
+    B = 0.0f;
+  } else {
+    A = -P.lh;
+    B = P.disc_trailer[k - P.n_disc_tractor];
+  }
+}
+
+// constraint bucket: obstacle rows the kernel instance can hold (0 = guidance off)
 inline int bucket_for(uint32_t n_obs, uint32_t flags) {
   if (flags & BRMPPI_GUIDANCE_OFF) return 0;
   if (n_obs <= 2) return 2;

@@ -153,12 +153,14 @@ __device__ __forceinline__ void stf(float* p, float v) {
 // the step into separately scheduled regions).
 __device__ __forceinline__ float sel(bool c, float a, float b) { return __builtin_unpredictable(c) ? a : b; }
 
-// Obstacle staged in LDS: centre relative to the tile origin, velocity; for
-// e = 2 the shape matrix Q = R' diag((mx+r)^-2, (my+r)^-2) R of eq. (16), for
-// e = 4 (e4 = 1) the rotation (co, so) into the obstacle frame and the
-// per-axis coefficients k = (m+r)^-4.
+// Obstacle row staged in LDS: the obstacle's centre relative to the tile
+// origin, velocity; for e = 2 the shape matrix Q = R' diag((mx+r)^-2,
+// (my+r)^-2) R of eq. (16); the rotation (co, so) into the obstacle frame and
+// the per-axis coefficients k = (m+r)^-e (e4 = 1 for e = 4); the row's
+// footprint disc (dA, dB).
 struct ObsL {
   float cx, cy, vx, vy, q11, q12, q22, e4, co, so, k0, k1;
+  float dA, dB;   // the row's footprint disc: centre p + dA e1 - dB f2
 };
 
 struct RefPoint {
@@ -372,6 +374,118 @@ __device__ __forceinline__ ObsRow obstacle_row_e4(const ObsL& ob, float px, floa
   return R;
 }
 
+// Kinematics of a footprint disc centre c = p + A e1 - B f2 along the drift
+// (inputs zero), for the rows of a footprint other than the rear axle (Sec.
+// IV-C): e1, e2 the tractor's heading and its left normal, f2, n2 the
+// trailer's; every quantity is P0 + A PA - B PB with the step's parts below.
+//   velocity  c'   = v e1 + A w1 e2 - B w2 n2
+//   accel.    c''  = a e1 + v w1 e2 + A (w1' e2 - w1^2 e1) - B (w2' n2 - w2^2 f2)
+//   jerk      c''' = -v w1^2 e1 + (2 a w1 + v w1') e2 + A (-3 w1 w1' e1 - w1^3 e2)
+//                    + B (3 w2 w2' f2 + (w2^3 - w2'') n2)
+// with w1 = th1', w2 = th2' of eq. (6) and their drift derivatives; and the
+// partials through which the inputs act: dc'/d delta, dc''/da, dc''/d delta.
+struct DiscBasis {
+  float f2x, f2y;                                  // position: P0 = p, PA = e1, PB = f2
+  float v0x, v0y, vAx, vAy, vBx, vBy;              // velocity
+  float a0x, a0y, aAx, aAy, aBx, aBy;              // drift acceleration
+  float j0x, j0y, jAx, jAy, jBx, jBy;              // drift jerk
+  float gAx, gAy, gBx, gBy;                        // d velocity / d delta (P0 = 0)
+  float ha0x, ha0y, haAx, haAy, haBx, haBy;        // d acceleration / d a
+  float hd0x, hd0y, hdAx, hdAy, hdBx, hdBy;        // d acceleration / d delta
+};
+
+__device__ __forceinline__ DiscBasis disc_basis(float v, float a, float c1, float s1, float cp, float sp, float tn,
+                                                float sec2, float inv_l1, float inv_l2, float ch) {
+  DiscBasis D;
+  const float e2x = -s1, e2y = c1;
+  D.f2x = c1 * cp + s1 * sp;          // theta2 = theta1 - phi
+  D.f2y = s1 * cp - c1 * sp;
+  const float n2x = -D.f2y, n2y = D.f2x;
+  const float kd = tn * inv_l1, dkd = sec2 * inv_l1;
+  const float W = inv_l2 * (sp - ch * cp * tn);             // w2 = v W
+  const float Wp = inv_l2 * (cp + ch * sp * tn);            // dW/dphi (d2W/dphi2 = -W)
+  const float Wd = -inv_l2 * ch * cp * sec2;                // dW/d delta
+  const float Wpd = inv_l2 * ch * sp * sec2;                // d2W/dphi d delta
+  const float w1 = v * kd, w2 = v * W, ph = w1 - w2;
+  const float w1d = a * kd;                                 // w1' along the drift
+  const float w2d = a * W + v * Wp * ph;                    // w2'
+  const float w2dd = 2.0f * a * Wp * ph - v * W * ph * ph + v * Wp * (w1d - w2d);   // w2''
+  D.v0x = v * c1;  D.v0y = v * s1;
+  D.vAx = w1 * e2x;  D.vAy = w1 * e2y;
+  D.vBx = w2 * n2x;  D.vBy = w2 * n2y;
+  D.a0x = a * c1 + v * w1 * e2x;  D.a0y = a * s1 + v * w1 * e2y;
+  D.aAx = w1d * e2x - w1 * w1 * c1;  D.aAy = w1d * e2y - w1 * w1 * s1;
+  D.aBx = w2d * n2x - w2 * w2 * D.f2x;  D.aBy = w2d * n2y - w2 * w2 * D.f2y;
+  const float j1 = -v * w1 * w1, j2 = 2.0f * a * w1 + v * w1d;
+  D.j0x = j1 * c1 + j2 * e2x;  D.j0y = j1 * s1 + j2 * e2y;
+  const float jA1 = -3.0f * w1 * w1d, jA2 = -w1 * w1 * w1;
+  D.jAx = jA1 * c1 + jA2 * e2x;  D.jAy = jA1 * s1 + jA2 * e2y;
+  const float jB1 = -3.0f * w2 * w2d, jB2 = w2dd - w2 * w2 * w2;
+  D.jBx = jB1 * D.f2x + jB2 * n2x;  D.jBy = jB1 * D.f2y + jB2 * n2y;
+  D.gAx = v * dkd * e2x;  D.gAy = v * dkd * e2y;
+  D.gBx = v * Wd * n2x;  D.gBy = v * Wd * n2y;
+  D.ha0x = c1;  D.ha0y = s1;
+  D.haAx = kd * e2x;  D.haAy = kd * e2y;
+  D.haBx = W * n2x;  D.haBy = W * n2y;
+  const float w2d_dl = a * Wd + v * Wpd * ph + v * Wp * (v * dkd - v * Wd);
+  D.hd0x = v * v * dkd * e2x;  D.hd0y = v * v * dkd * e2y;
+  D.hdAx = a * dkd * e2x - 2.0f * w1 * v * dkd * c1;  D.hdAy = a * dkd * e2y - 2.0f * w1 * v * dkd * s1;
+  D.hdBx = w2d_dl * n2x - 2.0f * w2 * v * Wd * D.f2x;  D.hdBy = w2d_dl * n2y - 2.0f * w2 * v * Wd * D.f2y;
+  return D;
+}
+
+// Row of an obstacle around a footprint disc (e = 2 or 4), eqs. (16)-(17):
+// per axis of the obstacle frame (y = R (c - p_o(t)), k = (m + r)^-e)
+// h = sum k y^e - 1 and its time derivatives along the drift from those of
+// y; hhat = h + Ts hd + Ts^2/2 hdd; Lf = Ts d hhat/dt along the drift
+// (obstacle motion included) = Ts (hd + Ts hdd + Ts^2/2 hddd); g = Ts (d
+// hhat/da, d hhat/d delta), which reach hhat through c' (delta) and c''.
+__device__ __forceinline__ ObsRow obstacle_row_disc(const ObsL& ob, const DiscBasis& D, float px, float py,
+                                                    float c1, float s1, float t, float Ts, float Ts2) {
+  const float A = ob.dA, B = ob.dB;
+  const float dx = px + A * c1 - B * D.f2x - (ob.cx + ob.vx * t);
+  const float dy = py + A * s1 - B * D.f2y - (ob.cy + ob.vy * t);
+  const float ux = D.v0x + A * D.vAx - B * D.vBx - ob.vx, uy = D.v0y + A * D.vAy - B * D.vBy - ob.vy;
+  const float wx = D.a0x + A * D.aAx - B * D.aBx, wy = D.a0y + A * D.aAy - B * D.aBy;
+  const float zx = D.j0x + A * D.jAx - B * D.jBx, zy = D.j0y + A * D.jAy - B * D.jBy;
+  const float gx = A * D.gAx - B * D.gBx, gy = A * D.gAy - B * D.gBy;
+  const float hax = D.ha0x + A * D.haAx - B * D.haBx, hay = D.ha0y + A * D.haAy - B * D.haBy;
+  const float hdx = D.hd0x + A * D.hdAx - B * D.hdBx, hdy = D.hd0y + A * D.hdAy - B * D.hdBy;
+  const float co = ob.co, so = ob.so;
+  const float y[2] = {co * dx + so * dy, -so * dx + co * dy};
+  const float yd[2] = {co * ux + so * uy, -so * ux + co * uy};
+  const float ydd[2] = {co * wx + so * wy, -so * wx + co * wy};
+  const float yddd[2] = {co * zx + so * zy, -so * zx + co * zy};
+  const float ydl[2] = {co * gx + so * gy, -so * gx + co * gy};          // d y_dot / d delta
+  const float ya[2] = {co * hax + so * hay, -so * hax + co * hay};       // d y_ddot / da
+  const float yddl[2] = {co * hdx + so * hdy, -so * hdx + co * hdy};     // d y_ddot / d delta
+  const bool e4 = ob.e4 != 0.0f;
+  const float k[2] = {ob.k0, ob.k1};
+  float h = -1.0f, hd = 0.0f, hdd = 0.0f, hddd = 0.0f, da = 0.0f, dd1 = 0.0f, dd2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float yy = y[i] * y[i];
+    // derivatives of k y^e: (f0, f1, f2, f3)
+    const float f0 = sel(e4, k[i] * yy * yy, k[i] * yy);
+    const float f1 = sel(e4, 4.0f * k[i] * yy * y[i], 2.0f * k[i] * y[i]);
+    const float f2 = sel(e4, 12.0f * k[i] * yy, 2.0f * k[i]);
+    const float f3 = sel(e4, 24.0f * k[i] * y[i], 0.0f);
+    h += f0;
+    hd += f1 * yd[i];
+    hdd += f2 * yd[i] * yd[i] + f1 * ydd[i];
+    hddd += f3 * yd[i] * yd[i] * yd[i] + 3.0f * f2 * yd[i] * ydd[i] + f1 * yddd[i];
+    da += f1 * ya[i];
+    dd1 += f1 * ydl[i];
+    dd2 += 2.0f * f2 * yd[i] * ydl[i] + f1 * yddl[i];
+  }
+  ObsRow R;
+  R.hhat = h + Ts * hd + 0.5f * Ts2 * hdd;
+  R.Lf = Ts * (hd + Ts * hdd + 0.5f * Ts2 * hddd);
+  R.g0 = Ts * (0.5f * Ts2 * da);
+  R.g1 = Ts * (Ts * dd1 + 0.5f * Ts2 * dd2);
+  return R;
+}
+
 // E4: the instance has super-ellipse obstacles (decided once per tile, so that
 // ellipse-only instances run a step loop without the e = 4 code)
 template <bool E4>
@@ -380,6 +494,19 @@ __device__ __forceinline__ ObsRow obstacle_row_any(const ObsL& ob, float px, flo
                                                    float inv_l1) {
   if (E4 && ob.e4 != 0.0f) return obstacle_row_e4(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
   return obstacle_row(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+}
+
+// the row of obstacle slot `ob`: at the rear axle (e = 2, or 4 with E4) or,
+// with DISC, around the slot's footprint disc
+template <bool E4, bool DISC>
+__device__ __forceinline__ ObsRow obstacle_row_sel(const ObsL& ob, const DiscBasis& D, float px, float py, float v,
+                                                   float a, float c1, float s1, float vkd, float sec2, float t,
+                                                   float Ts, float Ts2, float inv_l1) {
+  if constexpr (DISC) {
+    return obstacle_row_disc(ob, D, px, py, c1, s1, t, Ts, Ts2);
+  } else {
+    return obstacle_row_any<E4>(ob, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+  }
 }
 
 // value held by lane Q of each G-lane group, broadcast to the group (DPP quad
@@ -444,16 +571,27 @@ __device__ __forceinline__ Acc5 virtual_tree(Leaf& leaf) {
 }
 
 // Collision-penalty baseline (the paper's second MPPI baseline, Sec. V; its
-// form is not given): sum_o max(0, -h_o)^2 with h_o the obstacle function of
-// eq. (16) (e = 2 or 4) at the current position and time, in obstacle order
-// (every lane of a group sums all obstacles).
-template <bool E4>
+// form is not given): sum over the obstacle rows of max(0, -h)^2 with h the
+// obstacle function of eq. (16) (e = 2 or 4) at the row's point (the rear
+// axle, or with DISC its footprint disc centre) and the current time, in row
+// order (every lane of a group sums all rows).
+template <bool E4, bool DISC>
 __device__ __forceinline__ float collision_pen(const ObsL* __restrict__ sobs, int n_obs, float px, float py,
-                                               float t) {
+                                               float th1, float th2, float t) {
+  float c1 = 0.0f, s1 = 0.0f, c2 = 0.0f, s2 = 0.0f;
+  if constexpr (DISC) {
+    sincosf(th1, &s1, &c1);
+    sincosf(th2, &s2, &c2);
+  }
   float pen = 0.0f;
   for (int o = 0; o < n_obs; ++o) {
     const ObsL ob = sobs[o];
-    const float dx = px - (ob.cx + ob.vx * t), dy = py - (ob.cy + ob.vy * t);
+    float qx = px, qy = py;
+    if constexpr (DISC) {
+      qx = px + ob.dA * c1 - ob.dB * c2;
+      qy = py + ob.dA * s1 - ob.dB * s2;
+    }
+    const float dx = qx - (ob.cx + ob.vx * t), dy = qy - (ob.cy + ob.vy * t);
     float h;
     if (E4 && ob.e4 != 0.0f) {
       const float y0 = ob.co * dx + ob.so * dy, y1 = -ob.so * dx + ob.co * dy;
@@ -558,7 +696,7 @@ __device__ __forceinline__ float lane_value(float x) {
 // holds the same inputs, state and cost.
 // s_u / s_J (fused epilogue): the tile's applied inputs [3T][lds_stride] and
 // costs in LDS, at column t_local.
-template <int NOB, bool GUIDED, int G, bool PRE, bool E4>
+template <int NOB, bool GUIDED, int G, bool PRE, bool E4, bool DISC>
 __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
                                                int w0, int nw, int k0, float phi0, float* s_u, uint32_t lds_stride,
@@ -722,6 +860,8 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     if (GUIDED && guided) {
       const float sec2 = 1.0f + tn * tn;
       const float t = t0 + (float)tau * Ts;
+      DiscBasis DB;
+      if constexpr (DISC) DB = disc_basis(v, a, c1, s1, cp, sp, tn, sec2, inv_l1, inv_l2, ch);
 
       // hitch rows, eq. (18) split into h_s = dth_max - kappa v + s (th1 - th2),
       // first-order expansion hhat = h + Ts hd
@@ -765,7 +905,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           const int o = g + G * j;
           if constexpr (G == 1) {
             if (o < n_obs) {
-              const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+              const ObsRow R = obstacle_row_sel<E4, DISC>(sobs[o], DB, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
               O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
               acc_row(A, O[j]);
             }
@@ -773,7 +913,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
             // lanes past the last obstacle read a staged blank obstacle (Q =
             // 0): its row has hhat = -1 and Lf = g = +-0, so it adds exact
             // zeros to the sums, without a divergent branch or selects
-            const ObsRow R = obstacle_row_any<E4>(sobs[o], px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
+            const ObsRow R = obstacle_row_sel<E4, DISC>(sobs[o], DB, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
             O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
             acc_row(A, O[j]);
           }
@@ -808,7 +948,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     // --- stage cost r(x_tau, u*_tau, psi_tau), eq. (13) ---
     if constexpr (!kBatchCost) {
       float rc = stage_cost(P, rf, tg.sr, tg.cr, px, py, th1, th2, uj, uw, unu);
-      if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)tau * Ts);
+      if (penalty) rc += P.w_col * collision_pen<E4, DISC>(sobs, n_obs, px, py, th1, th2, t0 + (float)tau * Ts);
       J += (double)rc;
     } else {
       const bool mine = (int)(tau & (G - 1)) == g;
@@ -860,7 +1000,9 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       float sr, cr;
       step_sincos(r.th1, &sr, &cr);
       float rc = stage_cost(P, r, sr, cr, k_px, k_py, k_th1, k_th2, k_uj, k_uw, k_unu);
-      if (penalty) rc += P.w_col * collision_pen<E4>(sobs, n_obs, k_px, k_py, t0 + (float)(tau0 + (uint32_t)g) * Ts);
+      if (penalty)
+        rc += P.w_col * collision_pen<E4, DISC>(sobs, n_obs, k_px, k_py, k_th1, k_th2,
+                                                t0 + (float)(tau0 + (uint32_t)g) * Ts);
       J += (double)rc;
       if (n > 1) J += (double)lane_value<G, 1>(rc);
       if constexpr (G >= 4) {
@@ -894,7 +1036,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   }
   rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
-  if (penalty) rN += P.w_col * collision_pen<E4>(sobs, n_obs, px, py, t0 + (float)d.T * Ts);
+  if (penalty) rN += P.w_col * collision_pen<E4, DISC>(sobs, n_obs, px, py, th1, th2, t0 + (float)d.T * Ts);
   J += (double)rN;
   float Jf = (float)J;
   if (!isfinite(Jf)) Jf = INFINITY;
@@ -1487,9 +1629,11 @@ void k_rollout(const SolveDesc* __restrict__ descs,
     int nw = n_path - w0;
     if (nw > kPathWin) nw = kPathWin;
 
-    // stage obstacles (shape matrices) and the path window
+    // stage the obstacle rows (row r: obstacle r % n_objects around footprint
+    // disc r / n_objects) and the path window
     if (threadIdx.x < d.n_obs) {
-      const brmppi_obstacle o = d.obs[threadIdx.x];
+      const uint32_t oi = threadIdx.x % d.n_objects;
+      const brmppi_obstacle o = d.obs[oi];
       const float ax = o.mx + d.prm.r_disc, ay = o.my + d.prm.r_disc;
       const float iax = 1.0f / (ax * ax), iay = 1.0f / (ay * ay);
       float so, co;
@@ -1505,12 +1649,14 @@ void k_rollout(const SolveDesc* __restrict__ descs,
       L.e4 = (o.e == 4.0f) ? 1.0f : 0.0f;
       L.co = co;
       L.so = so;
-      L.k0 = iax * iax;
-      L.k1 = iay * iay;
+      L.k0 = (o.e == 4.0f) ? iax * iax : iax;   // (m + r)^-e
+      L.k1 = (o.e == 4.0f) ? iay * iay : iay;
+      disc_ab(d.prm, threadIdx.x / d.n_objects, L.dA, L.dB);
       s_obs[threadIdx.x] = L;
     } else if (threadIdx.x < BRMPPI_MAX_OBS) {
-      // blank slots (Q = 0, at rest): the rows of lanes past the last obstacle
-      s_obs[threadIdx.x] = ObsL{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      // blank slots (Q = 0, k = 0, at rest): the rows of lanes past the last
+      // obstacle row
+      s_obs[threadIdx.x] = ObsL{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     }
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
       float4 w = d.path[w0 + j];
@@ -1541,12 +1687,22 @@ void k_rollout(const SolveDesc* __restrict__ descs,
     const int g = (int)(threadIdx.x % G);
     const bool valid = s_raw < d.S;
     const uint32_t s = valid ? s_raw : d.S - 1;
-    if (d.any_e4)
-      rollout_sample<NOB, GUIDED, G, PRE, true>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
-                                                lds_stride, t_local, s_J);
-    else
-      rollout_sample<NOB, GUIDED, G, PRE, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0, phi0, s_u,
-                                                 lds_stride, t_local, s_J);
+    bool done = false;
+    if constexpr (GUIDED) {
+      if (d.any_disc) {
+        rollout_sample<NOB, GUIDED, G, PRE, true, true>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+                                                        phi0, s_u, lds_stride, t_local, s_J);
+        done = true;
+      }
+    }
+    if (!done) {
+      if (d.any_e4)
+        rollout_sample<NOB, GUIDED, G, PRE, true, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+                                                         phi0, s_u, lds_stride, t_local, s_J);
+      else
+        rollout_sample<NOB, GUIDED, G, PRE, false, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+                                                          phi0, s_u, lds_stride, t_local, s_J);
+    }
     __syncthreads();
     if (fused)
       tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);

@@ -21,7 +21,10 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "brmppi_internal.h"
+#include "served_core.h"
 
 using namespace brm;
 
@@ -42,73 +45,6 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(BRMPPI_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-using Clock = std::chrono::steady_clock;
-
-// ---------------------------------------------------------------------------
-// first-fit sub-allocator over the caller's device arena
-// ---------------------------------------------------------------------------
-struct Block {
-  char* ptr = nullptr;
-  size_t bytes = 0;
-};
-
-class Arena {
- public:
-  void init(void* base, size_t bytes) {
-    base_ = static_cast<char*>(base);
-    size_ = bytes;
-    free_.clear();
-    free_[0] = bytes;
-  }
-  Block alloc(size_t n) {
-    n = round_up(std::max<size_t>(n, 1), 256);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        const size_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > n) free_[off + n] = len - n;
-        used_ += n;
-        return Block{base_ + off, n};
-      }
-    }
-    return Block{};
-  }
-  void release(Block& b) {
-    if (!b.ptr) return;
-    size_t off = (size_t)(b.ptr - base_), len = b.bytes;
-    used_ -= len;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + len == next->first) {
-      len += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += len;
-        b = Block{};
-        return;
-      }
-    }
-    free_[off] = len;
-    b = Block{};
-  }
-  bool fits(size_t n) const {
-    n = round_up(std::max<size_t>(n, 1), 256);
-    for (auto& kv : free_)
-      if (kv.second >= n) return true;
-    return false;
-  }
-  size_t size() const { return size_; }
-  size_t used() const { return used_; }
-
- private:
-  char* base_ = nullptr;
-  size_t size_ = 0, used_ = 0;
-  std::map<size_t, size_t> free_;
-};
 
 // ---------------------------------------------------------------------------
 // static scratch of brmppi_solve_noalloc
@@ -123,6 +59,14 @@ constexpr int kMaxDevices = 64;
 std::mutex g_static_mu;                        // guards g_static_ptr
 char* g_static_ptr[kMaxDevices] = {};          // the array's address on each device
 std::mutex g_static_call_mu[kMaxDevices];      // one no-alloc call at a time per device
+
+// a roctx range over a scope (rocprofv3 --marker-trace shows it)
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // pinned host staging buffer (allocated at create; re-allocated only when a
 // call needs more, which `grows` counts)
@@ -151,7 +95,9 @@ struct Pinned {
   }
 };
 
-struct Controller {
+// (busy: a served request is in flight; warm_T: length of the resident warm
+// start, 0 = none)
+struct Controller : SlotState {
   Block mem;                  // unom (3*MAX_T floats) + plant (8 doubles)
   float* unom = nullptr;
   double* plant = nullptr;
@@ -159,9 +105,7 @@ struct Controller {
   float4* path = nullptr;
   uint32_t n_path = 0;
   float ds = 0.0f;
-  uint32_t warm_T = 0;        // length of the resident warm start, 0 = none
   bool plant_set = false;
-  bool busy = false;          // a served request is in flight
   brmppi_params params{};     // used by problems whose params pointer is NULL
 };
 
@@ -194,9 +138,16 @@ InputBlock input_block(uint32_t T, bool with_unom, uint32_t n_groups) {
   return b;
 }
 
-// normals per (sample, step): 3 inputs, 2 hitch rows, one per obstacle
-uint32_t normals_per_step(const brmppi_problem& p) {
-  return (p.flags & BRMPPI_GUIDANCE_OFF) ? 3u : 5u + p.n_obs;
+const brmppi_params& params_of(const brmppi_ctx* ctx, const brmppi_problem& p);
+
+// obstacle rows of a problem: one per (footprint disc, obstacle)
+uint32_t obstacle_rows(const brmppi_ctx* ctx, const brmppi_problem& p) {
+  return p.n_obs * n_discs(params_of(ctx, p));
+}
+
+// normals per (sample, step): 3 inputs, 2 hitch rows, one per obstacle row
+uint32_t normals_per_step(const brmppi_ctx* ctx, const brmppi_problem& p) {
+  return (p.flags & BRMPPI_GUIDANCE_OFF) ? 3u : 5u + obstacle_rows(ctx, p);
 }
 
 ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0,
@@ -263,28 +214,33 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
-struct Request {
-  uint64_t ticket = 0;
-  brmppi_problem prob{};
-  brmppi_params params{};
-  std::vector<brmppi_obstacle> obs;
-  std::vector<float> unom;
-  std::vector<float> result;
-  brmppi_stats st{};
-  int status = BRMPPI_PENDING;
-  bool done = false;
-  Clock::time_point t_submit;
-  Block scratch;
-};
-
-struct ServedBatch {
-  std::vector<Request*> reqs;
-  Block mem;              // descs + tiles + items + per-instance scratch
-  size_t out_off = 0;     // device offset of the packed outputs inside mem
-  std::vector<size_t> out_pos;  // float offset of each request's [stats(4) | u(3T)]
-  size_t out_floats = 0;
-  int slot = 0;
-  hipEvent_t done_ev = nullptr;
+// Device side of the served form (the queue, admission and the request
+// thread are served_core.h's): a batch's packed device block, its outputs in
+// the slot's pinned staging, its completion event and its trace range.
+struct HipServed {
+  brmppi_ctx* ctx = nullptr;
+  struct BatchState {
+    Block mem;                      // descs + tiles + items + per-instance scratch
+    size_t out_off = 0;             // offset of the packed outputs in the slot's pinned staging
+    std::vector<size_t> out_pos;    // float offset of each request's [stats(4) | u(3T)]
+    size_t out_floats = 0;
+    hipEvent_t done_ev = nullptr;
+    roctx_range_id_t range = 0;     // launch to completion
+  };
+  template <class B> int launch(B& b);
+  template <class B> int query(B& b);
+  template <class B> void retire(B& b);
+  template <class B> void abandon(B& b);
+  SlotState& controller(uint32_t id);
+  bool fits(size_t bytes);
+  template <class B> void on_launch(B& b) {
+    b.state.range = roctxRangeStartA("brmppi batch");
+  }
+  template <class B> void on_complete(B& b) {
+    roctxRangeStop(b.state.range);
+  }
+  void trace_push(const char* name) { roctxRangePushA(name); }
+  void trace_pop() { roctxRangePop(); }
 };
 
 // rollout launch shape: block size and variant (0 = one lane per sample,
@@ -311,7 +267,6 @@ struct brmppi_ctx {
   Arena arena;
   hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t n_streams = 1;
-  uint32_t max_inflight = 4096;
   uint32_t flags = 0;
   int n_cu = 256;
   std::string tune_path;
@@ -340,19 +295,11 @@ struct brmppi_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> pending_timing;
 
-  // served form
-  std::mutex mu;                // guards everything below and every device enqueue
-  std::condition_variable cv;
-  std::thread loop;
-  bool running = false;
-  uint64_t next_ticket = 1;
-  std::deque<Request*> queue;
-  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-  std::vector<ServedBatch> inflight;
+  // served form: the request queue and thread of served_core.h over HIP
+  HipServed served_dev;
+  ServedCore<HipServed> srv;
+  std::mutex& mu = srv.mu;      // guards the whole context and every device enqueue
   Pinned slot_pin[4];
-  bool slot_busy[4] = {false, false, false, false};
-  size_t n_active = 0;          // queued + running requests
-  uint64_t served_done = 0, served_failed = 0;
 
   // host resources (also on a failed create); device memory is the caller's
   ~brmppi_ctx() {
@@ -388,6 +335,8 @@ brmppi_params default_params() {
   P.alpha0 = 0.5f; P.alpha_lo = -1.0f; P.alpha_hi = 1.0f;
   P.h_eps = 1e-5f; P.w_col = 1000.0f;
   P.qh_j = P.W_j; P.qh_w = P.W_w; P.alpha_h = 0.5f;
+  P.n_disc_tractor = 1; P.disc_tractor[0] = 0.0f;   // the rear axle, eq. (16)
+  P.n_disc_trailer = 0;
   return P;
 }
 
@@ -400,8 +349,8 @@ const brmppi_params& params_of(const brmppi_ctx* ctx, const brmppi_problem& p) {
 // validation
 // ---------------------------------------------------------------------------
 bool finite_params(const brmppi_params& p) {
-  const float* f = reinterpret_cast<const float*>(&p);
-  for (size_t i = 0; i < sizeof(p) / sizeof(float); ++i)
+  const float* f = reinterpret_cast<const float*>(&p);   // every float field precedes the disc counts
+  for (size_t i = 0; i < offsetof(brmppi_params, n_disc_tractor) / sizeof(float); ++i)
     if (!std::isfinite(f[i])) return false;
   return true;
 }
@@ -413,6 +362,8 @@ int validate_params(const brmppi_params& P) {
   if (!(P.W_j + P.rho > 0) || !(P.W_w + P.rho > 0) || !(P.W_a + P.rho > 0) || P.rho < 0 || P.W_j < 0 ||
       P.W_w < 0 || P.W_a < 0)
     return fail(BRMPPI_EINVAL, "projection weights must be >= 0 with W + rho > 0");
+  if (P.n_disc_tractor > BRMPPI_MAX_DISCS || P.n_disc_trailer > BRMPPI_MAX_DISCS || n_discs(P) < 1)
+    return fail(BRMPPI_EINVAL, "footprint: 1..4 discs per body, at least one disc");
   return BRMPPI_OK;
 }
 
@@ -436,6 +387,8 @@ int validate(brmppi_ctx* ctx, const brmppi_problem* p) {
   if ((p->flags & BRMPPI_HITCH_QP) && (!(P.qh_j > 0) || !(P.qh_w > 0) || !(P.alpha_h > 0)))
     return fail(BRMPPI_EINVAL, "BRMPPI_HITCH_QP needs qh_j, qh_w and alpha_h positive");
   if (!std::isfinite(p->t0)) return fail(BRMPPI_EINVAL, "t0 must be finite");
+  if ((size_t)p->n_obs * n_discs(P) > BRMPPI_MAX_OBS)
+    return fail(BRMPPI_EINVAL, "obstacles times footprint discs exceed BRMPPI_MAX_OBS");
   for (uint32_t i = 0; i < p->n_obs; ++i) {
     const brmppi_obstacle& o = p->obs[i];
     if (o.e != 2.0f && o.e != 4.0f) return fail(BRMPPI_EINVAL, "obstacle exponent e must be 2 or 4");
@@ -472,7 +425,9 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.inv_ds = 1.0f / c.ds;
   d.S = p.S;
   d.T = p.T;
-  d.n_obs = p.n_obs;
+  d.n_obs = p.n_obs * n_discs(d.prm);      // obstacle rows
+  d.n_objects = p.n_obs;
+  d.any_disc = footprint_is_rear_axle(d.prm) ? 0u : 1u;
   d.flags = p.flags;
   d.n_path = c.n_path;
   d.instance = p.instance;
@@ -502,7 +457,7 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
   d.stats = out;
   d.u_new = out + 4;
   d.plant_x = c.plant;
-  d.n_normals = normals_per_step(p);
+  d.n_normals = (p.flags & BRMPPI_GUIDANCE_OFF) ? 3u : 5u + d.n_obs;
   d.noise = L.n_normals ? reinterpret_cast<float*>(base + L.off_noise) : nullptr;
   for (uint32_t i = 0; i < p.n_obs; ++i) {
     d.obs[i] = p.obs[i];
@@ -512,10 +467,10 @@ void fill_desc(SolveDesc& d, const brmppi_problem& p, const Controller& c, const
 
 // launch shape of a plain (single-instance) rollout
 LaunchShape plain_shape(brmppi_ctx* ctx, const brmppi_problem& p) {
-  const int bucket = bucket_for(p.n_obs, p.flags);
+  const int bucket = bucket_for(obstacle_rows(ctx, p), p.flags);
   LaunchShape s = ctx->forced.block ? ctx->forced : ctx->shape[bucket_index(bucket)][s_class(p.S)];
   if (bucket == 0 && s.variant > 1) s.variant = 1;        // unguided: one lane per sample
-  const size_t noise = (size_t)normals_per_step(p) * p.T * round_up(p.S, 256) * sizeof(float);
+  const size_t noise = (size_t)normals_per_step(ctx, p) * p.T * round_up(p.S, 256) * sizeof(float);
   if (variant_pre(s.variant) && noise > std::min(kMaxNoiseBytes, ctx->arena.size() / 2)) s.variant = 0;
   return s;
 }
@@ -531,7 +486,7 @@ size_t fused_lds(const brmppi_problem& p, const LaunchShape& sh) {
 
 ScratchLayout plain_layout(const brmppi_ctx* ctx, const brmppi_problem& p, const LaunchShape& sh) {
   const brmppi_problem* pp = &p;
-  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(p) : 0u, reduce_rows(&pp, 1, ctx->n_cu));
+  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(ctx, p) : 0u, reduce_rows(&pp, 1, ctx->n_cu));
 }
 
 hipEvent_t take_event(brmppi_ctx* ctx) {
@@ -591,7 +546,7 @@ int enqueue_noise(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, cons
 // lds > 0: the rollout reduces its own tiles (fused epilogue, no k_reduce)
 int enqueue_rollout_reduce(brmppi_ctx* ctx, hipStream_t st, const SolveDesc* d_desc, const brmppi_problem& p,
                            const ScratchLayout& L, const LaunchShape& sh, size_t lds) {
-  const int bucket = bucket_for(p.n_obs, p.flags);
+  const int bucket = bucket_for(obstacle_rows(ctx, p), p.flags);
   const uint32_t per_tile = sh.block / variant_lanes(sh.variant);
   const uint32_t grid = (p.S + per_tile - 1) / per_tile;
   int rc = timed(ctx, st, 0, [&] {
@@ -738,7 +693,7 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
   std::vector<int> ibi(n);
   size_t tiles_b[5] = {0, 0, 0, 0, 0};
   for (uint32_t i = 0; i < n; ++i) {
-    ibi[i] = bucket_index(bucket_for(ps[i]->n_obs, ps[i]->flags));
+    ibi[i] = bucket_index(bucket_for(obstacle_rows(ctx, *ps[i]), ps[i]->flags));
     tiles_b[ibi[i]] += (ps[i]->S + block_of(ibi[i]) - 1) / block_of(ibi[i]);
   }
   for (int bi = 0; bi < 4; ++bi) {
@@ -830,7 +785,7 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
     fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0, unom_dev,
               counter, out);
     // guidance-off instances inside a guided batch: the flag is honoured per tile
-    const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + p.n_obs));
+    const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + obstacle_rows(ctx, p)));
     const uint32_t pi = bp.inst_part[i], blk = bp.parts[pi].block;
     for (uint32_t s0 = 0; s0 < p.S; s0 += blk) tc.push_back({pi, cost, Tile{i, s0}});
     for (uint32_t k = 0; k < bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup; ++k) bp.ritems.push_back(Item{i, k});
@@ -1147,16 +1102,18 @@ size_t request_footprint(const brmppi_problem& p) {
   return L.bytes + sizeof(SolveDesc) + (tiles + items) * 8 + sizeof(float) * (4 + 6 * (size_t)p.T) + 8 * 256;
 }
 
-// launch one batch of admitted requests on stream slot `slot` (ctx->mu held)
-int launch_served(brmppi_ctx* ctx, ServedBatch& b) {
+// launch one batch of admitted requests on stream slot b.slot (ctx->mu held)
+template <class B>
+int HipServed::launch(B& b) {
   const uint32_t n = (uint32_t)b.reqs.size();
   std::vector<const brmppi_problem*> ps(n);
   for (uint32_t i = 0; i < n; ++i) ps[i] = &b.reqs[i]->prob;
   BatchPlan bp;
   plan_layout(ctx, ps.data(), n, bp);
-  b.mem = ctx->arena.alloc(bp.total);
-  if (!b.mem.ptr) return fail(BRMPPI_ENOMEM, "served batch does not fit");
-  char* base = b.mem.ptr;
+  BatchState& st = b.state;
+  st.mem = ctx->arena.alloc(bp.total);
+  if (!st.mem.ptr) return fail(BRMPPI_ENOMEM, "served batch does not fit");
+  char* base = st.mem.ptr;
   plan_fill(ctx, ps.data(), n, base, bp);
   hipStream_t s = ctx->streams[b.slot];
   int rc;
@@ -1167,184 +1124,54 @@ int launch_served(brmppi_ctx* ctx, ServedBatch& b) {
   if ((rc = enqueue_batch(ctx, s, base, bp, ctx->counters + 1 + b.slot, false))) return rc;
   HIPCHK(hipMemcpyAsync(pin + bp.header_bytes, base + bp.off_outs, bp.out_floats * sizeof(float),
                         hipMemcpyDeviceToHost, s));
-  b.out_pos = bp.out_pos;
-  b.out_floats = bp.out_floats;
-  b.out_off = bp.header_bytes;
-  if (!b.done_ev) HIPCHK(hipEventCreateWithFlags(&b.done_ev, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(b.done_ev, s));
+  st.out_pos = bp.out_pos;
+  st.out_floats = bp.out_floats;
+  st.out_off = bp.header_bytes;
+  if (!st.done_ev) HIPCHK(hipEventCreateWithFlags(&st.done_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(st.done_ev, s));
   return 0;
 }
 
-void retire_served(brmppi_ctx* ctx, ServedBatch& b) {
-  const float* pout = reinterpret_cast<const float*>(ctx->slot_pin[b.slot].ptr + b.out_off);
-  const auto now = Clock::now();
+template <class B>
+int HipServed::query(B& b) {
+  const hipError_t q = hipEventQuery(b.state.done_ev);
+  if (q == hipSuccess) return 0;
+  if (q == hipErrorNotReady) return 1;
+  return -1;
+}
+
+// results of a completed batch into its requests; its memory back to the arena
+template <class B>
+void HipServed::retire(B& b) {
+  BatchState& st = b.state;
+  const float* pout = reinterpret_cast<const float*>(ctx->slot_pin[b.slot].ptr + st.out_off);
   for (size_t i = 0; i < b.reqs.size(); ++i) {
     Request* r = b.reqs[i];
-    const float* o = pout + b.out_pos[i];
+    const float* o = pout + st.out_pos[i];
     r->status = (int)o[3];
     r->result.assign(o + 4, o + 4 + 3 * r->prob.T);
     r->st.J_min = o[0];
     r->st.Z = o[1];
     r->st.ess = o[2];
-    r->st.status = r->status;
-    r->st.latency_us = std::chrono::duration<double, std::micro>(now - r->t_submit).count();
-    r->done = true;
-    Controller& c = ctx->ctrl[r->prob.controller];
-    c.busy = false;
-    if (r->status == BRMPPI_OK) c.warm_T = r->prob.T;
-    ++ctx->served_done;
   }
-  ctx->arena.release(b.mem);
-  ctx->slot_busy[b.slot] = false;
+  ctx->arena.release(st.mem);
+  if (st.done_ev) (void)hipEventDestroy(st.done_ev);
+  st.done_ev = nullptr;
 }
 
-void fail_request(brmppi_ctx* ctx, Request* r, int code) {
-  r->status = code;
-  r->st.status = code;
-  r->done = true;
-  ++ctx->served_failed;
+// a failed batch: work of it that may already be enqueued on the slot's
+// stream finishes before its memory goes back to the arena
+template <class B>
+void HipServed::abandon(B& b) {
+  BatchState& st = b.state;
+  if (st.mem.ptr) (void)hipStreamSynchronize(ctx->streams[b.slot]);
+  ctx->arena.release(st.mem);
+  if (st.done_ev) (void)hipEventDestroy(st.done_ev);
+  st.done_ev = nullptr;
 }
 
-// fail every request of a batch; work of it that may already be enqueued on
-// the slot's stream finishes before its memory goes back to the arena
-void fail_batch(brmppi_ctx* ctx, ServedBatch& b, int code) {
-  for (Request* r : b.reqs) {
-    fail_request(ctx, r, code);
-    ctx->ctrl[r->prob.controller].busy = false;
-  }
-  if (b.mem.ptr) (void)hipStreamSynchronize(ctx->streams[b.slot]);
-  ctx->arena.release(b.mem);
-  if (b.done_ev) (void)hipEventDestroy(b.done_ev);
-  b.done_ev = nullptr;
-  ctx->slot_busy[b.slot] = false;
-}
-
-void request_loop(brmppi_ctx* ctx) {
-  (void)hipSetDevice(ctx->device);
-  std::unique_lock<std::mutex> lk(ctx->mu);
-  while (true) {
-    bool progressed = false;
-    // retire finished batches (in any order)
-    for (size_t i = 0; i < ctx->inflight.size();) {
-      hipError_t q = hipEventQuery(ctx->inflight[i].done_ev);
-      if (q == hipSuccess) {
-        retire_served(ctx, ctx->inflight[i]);
-        (void)hipEventDestroy(ctx->inflight[i].done_ev);
-        ctx->inflight.erase(ctx->inflight.begin() + i);
-        progressed = true;
-      } else if (q != hipErrorNotReady) {
-        fail_batch(ctx, ctx->inflight[i], BRMPPI_EDEVICE);   // also destroys its event
-        ctx->inflight.erase(ctx->inflight.begin() + i);
-        progressed = true;
-      } else {
-        ++i;
-      }
-    }
-    if (progressed) ctx->cv.notify_all();
-    // a destroyed context runs nothing more: queued requests fail, batches in
-    // flight drain
-    if (!ctx->running && !ctx->queue.empty()) {
-      for (Request* r : ctx->queue) fail_request(ctx, r, BRMPPI_ECANCELED);
-      ctx->queue.clear();
-      ctx->cv.notify_all();
-    }
-    // admit queued requests into a new batch on a free stream slot
-    int slot = -1;
-    for (uint32_t k = 0; k < ctx->n_streams; ++k)
-      if (!ctx->slot_busy[k]) {
-        slot = (int)k;
-        break;
-      }
-    if (slot >= 0 && !ctx->queue.empty()) {
-      ServedBatch b;
-      b.slot = slot;
-      size_t budget_bytes = 0;
-      std::vector<uint8_t> taken(ctx->ctrl.size(), 0);
-      for (auto it = ctx->queue.begin(); it != ctx->queue.end() && b.reqs.size() < BRMPPI_MAX_BATCH;) {
-        Request* r = *it;
-        Controller& c = ctx->ctrl[r->prob.controller];
-        // one request per controller per batch, in submission order
-        if (c.busy || taken[r->prob.controller]) {
-          taken[r->prob.controller] = 1;
-          ++it;
-          continue;
-        }
-        if (!r->prob.u_nom && c.warm_T != r->prob.T) {
-          // every earlier request of this controller has finished and none left
-          // a warm start of length T
-          fail_request(ctx, r, BRMPPI_ESTATE);
-          it = ctx->queue.erase(it);
-          progressed = true;
-          continue;
-        }
-        const size_t fp = request_footprint(r->prob);
-        if (!ctx->arena.fits(budget_bytes + fp)) {
-          if (b.reqs.empty() && ctx->inflight.empty()) {
-            // nothing runs that could free memory, and the context's persistent
-            // allocations never shrink: this request can never be admitted
-            fail_request(ctx, r, BRMPPI_ENOMEM);
-            it = ctx->queue.erase(it);
-            progressed = true;
-            continue;
-          }
-          taken[r->prob.controller] = 1;
-          ++it;
-          continue;
-        }
-        budget_bytes += fp;
-        taken[r->prob.controller] = 1;
-        b.reqs.push_back(r);
-        it = ctx->queue.erase(it);
-      }
-      if (progressed) ctx->cv.notify_all();
-      if (!b.reqs.empty()) {
-        for (Request* r : b.reqs) ctx->ctrl[r->prob.controller].busy = true;
-        ctx->slot_busy[slot] = true;
-        const int rc = launch_served(ctx, b);
-        if (rc != BRMPPI_OK) {
-          if (rc == BRMPPI_ENOMEM && b.mem.ptr == nullptr && !ctx->inflight.empty()) {
-            // could not get the packed block: requeue at the front and retry once
-            // a batch in flight has returned its memory
-            for (auto it = b.reqs.rbegin(); it != b.reqs.rend(); ++it) {
-              ctx->ctrl[(*it)->prob.controller].busy = false;
-              ctx->queue.push_front(*it);
-            }
-            ctx->slot_busy[slot] = false;
-          } else {
-            fail_batch(ctx, b, rc);
-            ctx->cv.notify_all();
-          }
-        } else {
-          ctx->inflight.push_back(std::move(b));
-        }
-        progressed = true;
-      }
-    }
-    if (!ctx->running && ctx->queue.empty() && ctx->inflight.empty()) break;
-    if (!progressed) {
-      if (ctx->inflight.empty() && ctx->queue.empty())
-        ctx->cv.wait_for(lk, std::chrono::milliseconds(5));
-      else {
-        lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
-        lk.lock();
-      }
-    }
-  }
-}
-
-int copy_problem(const brmppi_ctx* ctx, Request& r, const brmppi_problem* p) {
-  r.prob = *p;
-  r.params = params_of(ctx, *p);
-  r.prob.params = &r.params;
-  r.obs.assign(p->obs, p->obs + p->n_obs);
-  r.prob.obs = r.obs.empty() ? nullptr : r.obs.data();
-  if (p->u_nom) {
-    r.unom.assign(p->u_nom, p->u_nom + 3 * p->T);
-    r.prob.u_nom = r.unom.data();
-  }
-  return 0;
-}
+SlotState& HipServed::controller(uint32_t id) { return ctx->ctrl[id]; }
+bool HipServed::fits(size_t bytes) { return ctx->arena.fits(bytes); }
 
 int load_tune(brmppi_ctx* ctx) {
   if (ctx->tune_path.empty()) return 0;
@@ -1429,7 +1256,7 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
   ctx->arena.init(cfg->arena, cfg->arena_bytes);
   ctx->n_streams = cfg->n_streams;
   for (uint32_t k = 0; k < cfg->n_streams; ++k) ctx->streams[k] = static_cast<hipStream_t>(cfg->streams[k]);
-  ctx->max_inflight = cfg->max_inflight ? cfg->max_inflight : 4096;
+  ctx->srv.configure(cfg->n_streams, cfg->max_inflight);
   ctx->flags = cfg->flags;
   if (cfg->autotune_cache) ctx->tune_path = cfg->autotune_cache;
   int ncu = 0;
@@ -1471,21 +1298,18 @@ int brmppi_create(const brmppi_config* cfg, brmppi_ctx** out) {
     if (e != hipSuccess) return fail(BRMPPI_EDEVICE, std::string("context init: ") + hipGetErrorString(e));
   }
   load_tune(ctx.get());
-  ctx->running = true;
   brmppi_ctx* raw = ctx.release();
-  raw->loop = std::thread(request_loop, raw);
+  raw->served_dev.ctx = raw;
+  raw->srv.start(raw->served_dev);
   *out = raw;
   return BRMPPI_OK;
 }
 
 int brmppi_destroy(brmppi_ctx* ctx) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
-  {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->running = false;
-  }
-  ctx->cv.notify_all();
-  if (ctx->loop.joinable()) ctx->loop.join();
+  // queued requests fail with ECANCELED, batches in flight drain, the request
+  // thread ends
+  ctx->srv.stop();
   for (uint32_t k = 0; k < ctx->n_streams; ++k) (void)hipStreamSynchronize(ctx->streams[k]);
   drop_graph(ctx);
   collect_timing(ctx);
@@ -1503,8 +1327,8 @@ int brmppi_get_info(brmppi_ctx* ctx, brmppi_info* out) {
   out->pinned_grows = pg;
   out->arena_bytes = ctx->arena.size();
   out->arena_used = ctx->arena.used();
-  out->served_done = ctx->served_done;
-  out->served_failed = ctx->served_failed;
+  out->served_done = ctx->srv.done_count();
+  out->served_failed = ctx->srv.failed_count();
   return BRMPPI_OK;
 }
 
@@ -1652,6 +1476,7 @@ int brmppi_closed_loop(brmppi_ctx* ctx, const brmppi_problem* p, uint32_t n_upda
 
 int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket) {
   if (!ctx || !ticket) return fail(BRMPPI_EINVAL, "null argument");
+  TraceRange tr("brmppi submit");
   std::lock_guard<std::mutex> lk(ctx->mu);
   // a missing warm start is allowed when an earlier queued request of the same
   // controller will leave one; the request thread re-checks at launch
@@ -1670,53 +1495,47 @@ int brmppi_submit(brmppi_ctx* ctx, const brmppi_problem* p, uint64_t* ticket) {
   }
   const size_t fp = request_footprint(*p);
   if (fp > ctx->arena.size()) return fail(BRMPPI_ENOMEM, "request can never fit in the arena");
-  if (ctx->n_active >= ctx->max_inflight) return fail(BRMPPI_EAGAIN, "max_inflight requests queued");
   std::unique_ptr<Request> r(new Request());
-  r->ticket = ctx->next_ticket++;
-  copy_problem(ctx, *r, p);
-  r->t_submit = Clock::now();
-  Request* raw = r.get();
-  ctx->reqs[raw->ticket] = std::move(r);
-  ctx->queue.push_back(raw);
-  ctx->n_active++;
-  *ticket = raw->ticket;
-  ctx->cv.notify_all();
-  return BRMPPI_OK;
+  copy_problem(*r, *p, params_of(ctx, *p));
+  r->footprint = fp;
+  rc = ctx->srv.submit(std::move(r), ticket);
+  if (rc == BRMPPI_EAGAIN) return fail(rc, "max_inflight requests queued or unpolled");
+  return rc;
 }
+
+namespace {
+int served_status(int rc) {
+  switch (rc) {
+    case BRMPPI_OK:
+    case BRMPPI_PENDING:
+      return rc;
+    case BRMPPI_ENOTICKET:
+      return fail(rc, "unknown or consumed ticket");
+    case BRMPPI_ETIMEDOUT:
+      return fail(rc, "deadline passed");
+    case BRMPPI_EINVAL:
+      return fail(rc, "u_out is NULL");
+    case BRMPPI_ECANCELED:
+      return fail(rc, "the context was destroyed before the request was admitted");
+    case BRMPPI_ENOMEM:
+      return fail(rc, "the request can never fit in the arena's free space");
+    case BRMPPI_ESTATE:
+      return fail(rc, "no resident warm start of the request's horizon");
+    default:
+      return fail(rc, "request failed or had only non-finite costs");
+  }
+}
+}  // namespace
 
 int brmppi_poll(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  auto it = ctx->reqs.find(ticket);
-  if (it == ctx->reqs.end()) return fail(BRMPPI_ENOTICKET, "unknown or consumed ticket");
-  Request* r = it->second.get();
-  if (!r->done) return BRMPPI_PENDING;
-  if (!u_out) return fail(BRMPPI_EINVAL, "u_out is NULL");
-  const int status = r->status;
-  if (!r->result.empty()) std::memcpy(u_out, r->result.data(), sizeof(float) * r->result.size());
-  if (st) *st = r->st;
-  ctx->reqs.erase(it);
-  ctx->n_active--;
-  if (status != BRMPPI_OK) return fail(status, "request failed or had only non-finite costs");
-  return BRMPPI_OK;
+  return served_status(ctx->srv.poll(ticket, u_out, st));
 }
 
 int brmppi_wait(brmppi_ctx* ctx, uint64_t ticket, float* u_out, brmppi_stats* st, uint32_t timeout_ms) {
   if (!ctx) return fail(BRMPPI_EINVAL, "null context");
-  const auto deadline = Clock::now() + std::chrono::milliseconds(timeout_ms);
-  while (true) {
-    {
-      std::unique_lock<std::mutex> lk(ctx->mu);
-      auto it = ctx->reqs.find(ticket);
-      if (it == ctx->reqs.end()) return fail(BRMPPI_ENOTICKET, "unknown or consumed ticket");
-      if (!it->second->done) {
-        if (Clock::now() >= deadline) return fail(BRMPPI_ETIMEDOUT, "deadline passed");
-        ctx->cv.wait_for(lk, std::chrono::microseconds(200));
-        continue;
-      }
-    }
-    return brmppi_poll(ctx, ticket, u_out, st);
-  }
+  return served_status(ctx->srv.wait(ticket, u_out, st, timeout_ms));
 }
 
 int brmppi_set_launch(brmppi_ctx* ctx, uint32_t block, uint32_t variant) {
@@ -1749,12 +1568,7 @@ int brmppi_autotune(brmppi_ctx* ctx) {
     path[4 * i + 2] = 0.0f;
     path[4 * i + 3] = 0.0f;
   }
-  brmppi_params P{};
-  P.Ts = 0.05f; P.l1 = 4.0f; P.lh = 0.5f; P.l2 = 10.0f; P.dtheta_max = 0.7f; P.kappa = 0.05f; P.r_disc = 1.0f;
-  P.Qc = 2; P.Ql = 2; P.Qth1 = 1; P.Qth2 = 1; P.R_j = 0.05f; P.R_w = 0.05f; P.mu = 0.5f; P.nu_bar = 2;
-  P.W_j = 1; P.W_w = 11.1f; P.W_a = 25; P.rho = 0.1f; P.j_lo = -2; P.j_hi = 2; P.w_lo = -0.9f; P.w_hi = 0.9f;
-  P.alpha0 = 0.5f; P.alpha_lo = -1; P.alpha_hi = 1; P.sigma_j = 1; P.sigma_w = 0.3f; P.sigma_nu = 0.5f;
-  P.sigma_a = 0.2f; P.h_eps = 1e-5f;
+  const brmppi_params P = default_params();
   hipStream_t s = ctx->streams[0];
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

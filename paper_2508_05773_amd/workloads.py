@@ -39,6 +39,9 @@ FLAG_COLLISION_PENALTY = 16  # baseline: w_col * sum_o max(0, -h_o)^2 added to t
 FLAG_HITCH_QP = 32      # closed loop: hitch-angle stabiliser QP on the applied input
 
 
+MAX_DISCS = 4   # footprint discs per body (tractor, trailer)
+
+
 def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
                 dtheta_max=0.7, kappa=0.05, **over) -> dict:
     """Full explicit parameter set (float32-representable values).
@@ -67,9 +70,22 @@ def make_params(Ts, sigma=(1.0, 0.3, 0.5), l1=4.0, lh=0.5, l2=10.0,
         sigma_j=sj, sigma_w=sw, sigma_nu=sn, sigma_a=sa, h_eps=1e-5, w_col=1000.0,
         qh_j=1.0 / sj ** 2, qh_w=1.0 / sw ** 2, alpha_h=0.5,
     )
+    discs_t = over.pop("disc_tractor", (0.0,))
+    discs_r = over.pop("disc_trailer", ())
+    if not 1 <= len(discs_t) + len(discs_r) or len(discs_t) > MAX_DISCS or len(discs_r) > MAX_DISCS:
+        raise ValueError("footprint: 1..8 discs, at most 4 on each body")
     p.update(over)
     # round every value to float32 so both sides see identical numbers
-    return {k: float(np.float32(p[k])) for k in PARAM_FIELDS}
+    out = {k: float(np.float32(p[k])) for k in PARAM_FIELDS}
+    # footprint discs (Sec. IV-C): offsets ahead of the tractor's rear axle and
+    # behind the hitch along the trailer; the default is the rear axle alone
+    out["disc_tractor"] = [float(np.float32(v)) for v in discs_t]
+    out["disc_trailer"] = [float(np.float32(v)) for v in discs_r]
+    return out
+
+
+def n_discs(params: dict) -> int:
+    return len(params.get("disc_tractor", (0.0,))) + len(params.get("disc_trailer", ()))
 
 
 def params_array(p: dict) -> np.ndarray:

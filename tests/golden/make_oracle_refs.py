@@ -51,7 +51,8 @@ def fingerprint(p) -> str:
     h = hashlib.sha256()
     for a in (p.x0, p.u_nom, p.obstacles, p.path):
         h.update(np.ascontiguousarray(a, dtype=np.float32).tobytes())
-    h.update(np.array([p.params[k] for k in sorted(p.params)], np.float64).tobytes())
+    for k in sorted(p.params):
+        h.update(np.asarray(p.params[k], np.float64).reshape(-1).tobytes())
     h.update(repr((p.S, p.T, p.ds, p.lam, p.seed, p.instance, p.t0, p.flags)).encode())
     return h.hexdigest()[:16]
 

@@ -113,6 +113,7 @@ def test_default_params_without_a_device():
     want = W.make_params(0.05)
     for k in B.PARAM_FIELDS:
         assert np.float32(got[k]) == np.float32(want[k]), k
+    assert got["disc_tractor"] == want["disc_tractor"] == [0.0] and got["disc_trailer"] == want["disc_trailer"] == []
     assert B.lib().brmppi_default_params(None) == B.EINVAL
     assert B.lib().brmppi_set_params(None, 0, None) == B.EINVAL
     assert B.lib().brmppi_get_info(None, None) == B.EINVAL

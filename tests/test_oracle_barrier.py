@@ -6,6 +6,12 @@
 3. hd and hdd are the time derivatives of h along the exact (fine-step RK4)
    flow of the drift, for static and moving obstacles.
 4. The rows Lf, g and the h_eps guard match the definitions of eq. (9).
+5. Footprint discs (Sec. IV-C): the barrier around a disc centre p + A e1 - B f2
+   (tractor discs ahead of the rear axle, trailer discs behind the hitch)
+   against the same sympy derivation with the centre substituted, central
+   differences and the RK4 flow; the rear-axle disc (0, 0) is eq. (16) as
+   printed, bit for bit; rows come disc by disc, obstacles in order, with one
+   auxiliary normal each; the collision penalty sums every (disc, obstacle).
 """
 import math
 
@@ -175,3 +181,98 @@ def test_h_eps_guard(orc):
         hraw, hh, _, _ = orc.rows(prob, xx, 0.0)
         assert hraw[0] == pytest.approx(off, abs=1e-15)
         assert hh[0] == pytest.approx(want, rel=1e-12, abs=1e-18)
+
+
+def _rand_disc(rng, prm):
+    """a tractor disc ahead of (or behind) the rear axle, or a trailer disc"""
+    if rng.uniform() < 0.5:
+        return rng.uniform(-1.0, 4.0), 0.0
+    return -prm["lh"], rng.uniform(0.5, 9.0)
+
+
+@pytest.mark.parametrize("e", [2, 4])
+def test_disc_barrier_matches_symbolic(orc, e):
+    F = SR.disc_funcs(exponent=e)
+    rng = np.random.default_rng(20 + e)
+    prm = W.make_params(0.05)
+    for _ in range(40):
+        x, o, tt = _rand_state(rng), _rand_obs(rng, e=float(e)), rng.uniform(0, 3)
+        A, Bd = _rand_disc(rng, prm)
+        D = orc.disc_barrier(x, tt, o, A, Bd, prm)
+        args = SR.disc_args(x, tt, prm, o, A, Bd)
+        for k in ("h", "hd", "hdd", "hhat"):
+            assert D[k] == pytest.approx(F[k](*args), rel=1e-10, abs=1e-10), (k, A, Bd)
+        for i in range(8):
+            assert D["grad"][i] == pytest.approx(F["grad"][i](*args), rel=1e-9, abs=1e-9), (i, A, Bd)
+        assert D["dt"] == pytest.approx(F["dt"](*args), rel=1e-9, abs=1e-9)
+
+
+def test_rear_axle_disc_is_eq16(orc):
+    rng = np.random.default_rng(31)
+    prm = W.make_params(0.05)
+    for e in (2, 4):
+        for _ in range(20):
+            x, o, tt = _rand_state(rng), _rand_obs(rng, e=float(e)), rng.uniform(0, 3)
+            a, b = orc.obstacle_barrier(x, tt, o, prm), orc.disc_barrier(x, tt, o, 0.0, 0.0, prm)
+            for k in ("h", "hd", "hdd", "hhat", "dt"):
+                assert a[k] == b[k]
+            assert np.array_equal(a["grad"], b["grad"])
+
+
+@pytest.mark.parametrize("e", [2, 4])
+def test_disc_gradients_finite_difference_and_flow(orc, e):
+    rng = np.random.default_rng(40 + e)
+    prm = W.make_params(0.05)
+    eps, dt = 1e-6, 1e-3
+    for _ in range(20):
+        x, o, tt = _rand_state(rng), _rand_obs(rng, e=float(e)), rng.uniform(0, 3)
+        A, Bd = _rand_disc(rng, prm)
+        D = orc.disc_barrier(x, tt, o, A, Bd, prm)
+        for i in range(8):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += eps
+            xm[i] -= eps
+            fd = (orc.disc_barrier(xp, tt, o, A, Bd, prm)["hhat"] -
+                  orc.disc_barrier(xm, tt, o, A, Bd, prm)["hhat"]) / (2 * eps)
+            assert D["grad"][i] == pytest.approx(fd, rel=1e-6, abs=1e-7), i
+        fwd = _rk4_flow(orc, x, prm, dt, 2)
+        bwd = _rk4_flow(orc, x, prm, -dt, 2)
+        hs = {k: orc.disc_barrier(xs, tt + k * dt, o, A, Bd, prm)["h"]
+              for k, xs in ((1, fwd[1]), (2, fwd[2]), (-1, bwd[1]), (-2, bwd[2]), (0, x))}
+        hd_fd = (-hs[2] + 8 * hs[1] - 8 * hs[-1] + hs[-2]) / (12 * dt)
+        hdd_fd = (-hs[2] + 16 * hs[1] - 30 * hs[0] + 16 * hs[-1] - hs[-2]) / (12 * dt * dt)
+        assert D["hd"] == pytest.approx(hd_fd, rel=1e-6, abs=1e-7)
+        assert D["hdd"] == pytest.approx(hdd_fd, rel=1e-4, abs=1e-5)
+
+
+def test_disc_rows_order_and_penalty(orc):
+    """rows: hitch(+), hitch(-), then every (disc, obstacle), disc by disc;
+    Lf and g of each against sympy at that disc; one normal per row; the
+    collision penalty sums max(0, -h)^2 over every (disc, obstacle)"""
+    F2, F4 = SR.disc_funcs(exponent=2), SR.disc_funcs(exponent=4)
+    rng = np.random.default_rng(7)
+    prm = W.make_params(0.05, disc_tractor=(0.0, 2.5), disc_trailer=(1.0, 6.0))
+    prob = W.random_small(2, n_obs=3)
+    obs = prob.obstacles.copy()
+    obs[1, 5] = 4.0
+    prob = prob.copy(obstacles=obs, params=prm)
+    dl = orc.discs(prm)
+    assert dl == [(0.0, 0.0), (2.5, 0.0), (-prm["lh"], 1.0), (-prm["lh"], 6.0)]
+    op = orc.OracleProblem(prob)
+    assert op.n_c == 2 + 4 * 3 and op.n_normals == 5 + 4 * 3
+    for _ in range(10):
+        x, tt = _rand_state(rng), rng.uniform(0, 2)
+        hraw, hh, G, Lf = orc.rows(prob, x, tt)
+        assert len(hh) == 14
+        for k, (A, Bd) in enumerate(dl):
+            for o_idx, o in enumerate(prob.obstacles):
+                i = 2 + k * 3 + o_idx
+                F = F4 if o[5] == 4.0 else F2
+                args = SR.disc_args(x, tt, prm, o, A, Bd)
+                assert hraw[i] == pytest.approx(F["hhat"](*args), rel=1e-10, abs=1e-11)
+                assert Lf[i] == pytest.approx(F["Lf"](*args), rel=1e-9, abs=1e-10)
+                assert G[i, 0] == pytest.approx(F["g0"](*args), rel=1e-9, abs=1e-12)
+                assert G[i, 1] == pytest.approx(F["g1"](*args), rel=1e-9, abs=1e-12)
+        pen = orc.collision_penalty(x, tt, prob.obstacles, prm)
+        want = sum(min(0.0, orc.disc_barrier(x, tt, o, A, Bd, prm)["h"]) ** 2 for A, Bd in dl for o in prob.obstacles)
+        assert pen == pytest.approx(prm["w_col"] * want, rel=1e-12, abs=1e-300)

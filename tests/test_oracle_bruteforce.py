@@ -68,7 +68,7 @@ def _problem(e=2.0):
 @pytest.mark.parametrize("e", [2, 4])
 def test_bruteforce_s4_t3(orc, e):
     p = _problem(float(e))
-    P = {k: mp.mpf(v) for k, v in p.params.items()}
+    P = {k: mp.mpf(v) for k, v in p.params.items() if not isinstance(v, list)}
     nc = p.n_obs + 2
     K = 5 + p.n_obs          # normals: 3 inputs, hitch(+), hitch(-), obstacle 0
     rng = np.random.default_rng(11)
