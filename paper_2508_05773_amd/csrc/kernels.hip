@@ -1098,13 +1098,36 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Device-scope ordering for the "last block" patterns.  A publisher needs
-// only a release (its stores written back past its XCD's L2 before the
-// counter increment); the block that sees the last increment needs only an
-// acquire (stale lines dropped before it reads).  A full __threadfence() would
-// also invalidate the L2 of every publisher's XCD under blocks still running.
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// Hand-off of partial results between blocks (the "last block" patterns).
+// The partials are written and read only as device-scope relaxed atomics:
+// such a store writes through its XCD's L2 and such a load does not take a
+// stale line from the reader's L2, so each partial is coherent across the
+// XCDs by itself.  A publisher then needs only every wave's stores complete
+// (vmcnt drained) before the block's counter increment, and the block that
+// sees the last increment reads with those loads after it.  A release fence
+// at device scope would instead write back every dirty line of the XCD's L2
+// (and an acquire invalidate it), which stalls every block on that XCD: one
+// such write-back per work item cost the batched reduce a quarter of its
+// time.
+typedef __attribute__((address_space(1))) float glb_float;
+__device__ __forceinline__ void pub_st(float* p, float v) {
+  __hip_atomic_store((glb_float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void pub_st4(float4* p, float4 v) {
+  pub_st(&p->x, v.x);
+  pub_st(&p->y, v.y);
+  pub_st(&p->z, v.z);
+  pub_st(&p->w, v.w);
+}
+__device__ __forceinline__ float pub_ld(const float* p) {
+  return __hip_atomic_load((const glb_float*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float4 pub_ld4(const float4* p) {
+  return make_float4(pub_ld(&p->x), pub_ld(&p->y), pub_ld(&p->z), pub_ld(&p->w));
+}
+// this wave's stores complete; also a compiler barrier, so that no store
+// moves past it
+__device__ __forceinline__ void pub_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // grab the next work item (persistent) or take blockIdx.x (direct launch)
 __device__ __forceinline__ bool next_item(uint32_t it, uint32_t n_items, uint32_t* ctr_next, uint32_t* s_slot,
@@ -1121,9 +1144,11 @@ __device__ __forceinline__ bool next_item(uint32_t it, uint32_t n_items, uint32_
   return ix < n_items;
 }
 
+// The last block to finish resets the queue for the next launch (a graph
+// replay).  Only the two counters take part: a block increments done after
+// its last grab of next has returned, so no fence is needed.
 __device__ __forceinline__ void finish_persistent(uint32_t* next, uint32_t* done) {
   if (threadIdx.x == 0) {
-    fence_release();
     const uint32_t k = atomicAdd(done, 1u);
     if (k == gridDim.x - 1) {
       atomicExch(next, 0u);
@@ -1309,17 +1334,17 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
   const uint32_t r0 = threadIdx.x;
   float pre[kPre];
 #pragma unroll
-  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? gld(d.rpart + (size_t)k * R + r0) : 0.0f;
+  for (int k = 0; k < kPre; ++k) pre[k] = (r0 < R && (uint32_t)k < nW) ? pub_ld(d.rpart + (size_t)k * R + r0) : 0.0f;
   // this thread's first group partial is loaded once, for the minimum and the sums
-  const float4 w_first = threadIdx.x < nW ? gld4(d.wpart + threadIdx.x) : make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
+  const float4 w_first = threadIdx.x < nW ? pub_ld4(d.wpart + threadIdx.x) : make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
   float mloc = w_first.x;
   for (uint32_t c = threadIdx.x + nt; c < nW; c += nt) {
-    mloc = fminf(mloc, gld4(d.wpart + c).x);
+    mloc = fminf(mloc, pub_ld(&d.wpart[c].x));
   }
   const float m = block_min(mloc, s_red);
   float zl = 0.0f, z2l = 0.0f;
   for (uint32_t c = threadIdx.x; c < nW; c += nt) {
-    const float4 w = c == threadIdx.x ? w_first : gld4(d.wpart + c);
+    const float4 w = c == threadIdx.x ? w_first : pub_ld4(d.wpart + c);
     const float sc = (m < INFINITY && w.x < INFINITY) ? expf(-(w.x - m) * d.inv_lambda) : 0.0f;
     lds_put(s_scale + c, sc);
     zl += sc * w.y;
@@ -1338,14 +1363,14 @@ __device__ void finalize_instance(const SolveDesc& d, float* s_scale, float* s_r
         const bool use_pre = (c == 0) && (r == r0);
         float v[kPre];
 #pragma unroll
-        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : gld(col + (size_t)(c + k) * R);
+        for (int k = 0; k < kPre; ++k) v[k] = use_pre ? pre[k] : pub_ld(col + (size_t)(c + k) * R);
 #pragma unroll
         for (int k = 0; k < kPre; ++k) acc += lds(s_scale + c + k) * v[k];
       }
 #pragma unroll
       for (int k = 0; k < kPre; ++k) {
         if (c + k < nW) {
-          const float vk = (c == 0 && r == r0) ? pre[k] : gld(col + (size_t)(c + k) * R);
+          const float vk = (c == 0 && r == r0) ? pre[k] : pub_ld(col + (size_t)(c + k) * R);
           acc += lds(s_scale + c + k) * vk;
         }
       }
@@ -1445,10 +1470,10 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
   {
     const float* __restrict__ col = d.urow + (size_t)gu0 * R + (t < R ? t : 0);
 #pragma unroll
-    for (int u = 0; u < kGroupUnits; ++u) v0[u] = gld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
+    for (int u = 0; u < kGroupUnits; ++u) v0[u] = pub_ld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
   }
   float4 up = make_float4(INFINITY, 0.0f, 0.0f, 0.0f);
-  if (t < nu_g) up = gld4(d.upart + gu0 + t);
+  if (t < nu_g) up = pub_ld4(d.upart + gu0 + t);
   const float mg = block_min(up.x, s_red);
   if (t < nu_g) {
     lds_put(s_up + t, up);
@@ -1461,7 +1486,7 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
   if (t == tz) {
     float z, z2;
     group_sums(s_up, s_sig, nu_g, z, z2);
-    gst4(d.wpart + grp, make_float4(mg, z, z2, 0.0f));
+    pub_st4(d.wpart + grp, make_float4(mg, z, z2, 0.0f));
   }
   // one row: its unit sums in v, the scales read kChunk at a time (in bounds,
   // before any of them is used)
@@ -1476,7 +1501,7 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
       for (int k = 0; k < kChunk; ++k)
         if ((uint32_t)(c + k) < nu_g) acc = unit_row_term(acc, sg[k], v[c + k]);
     }
-    gst(d.rpart + (size_t)grp * R + r, acc);
+    pub_st(d.rpart + (size_t)grp * R + r, acc);
   };
   if (t < R) row_sum(t, v0);
   for (uint32_t r = t + nt; r < R; r += nt) {
@@ -1484,7 +1509,7 @@ __device__ __forceinline__ void group_merge(const SolveDesc& d, uint32_t grp, ui
     const float* __restrict__ col = d.urow + (size_t)gu0 * R + r;
     float v[kGroupUnits];
 #pragma unroll
-    for (int u = 0; u < kGroupUnits; ++u) v[u] = gld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
+    for (int u = 0; u < kGroupUnits; ++u) v[u] = pub_ld(col + (size_t)min((uint32_t)u, nu_g - 1) * R);
     row_sum(r, v);
   }
 }
@@ -1526,7 +1551,7 @@ __device__ __forceinline__ void tile_epilogue(const SolveDesc& d, uint32_t s0, u
   if (t < nu_tile) {
     float z, z2;
     unit_sums(s_gam + kUnit * t, z, z2);
-    gst4(d.upart + u0 + t, make_float4(lds(s_mu + t), z, z2, 0.0f));
+    pub_st4(d.upart + u0 + t, make_float4(lds(s_mu + t), z, z2, 0.0f));
   }
   for (uint32_t it = t; it < nu_tile * R; it += nt) {
     const uint32_t j = it / R, r = it - j * R;
@@ -1544,31 +1569,25 @@ __device__ __forceinline__ void tile_epilogue(const SolveDesc& d, uint32_t s0, u
 #pragma unroll
       for (int k = 0; k < kChunk; ++k) acc = unit_row_term(acc, g8[k], u8[k]);
     }
-    gst(d.urow + (size_t)(u0 + j) * R + r, acc);
+    pub_st(d.urow + (size_t)(u0 + j) * R + r, acc);
   }
   // publish the tile's units; the last tile of the group merges it
   const uint32_t grp = u0 / kGroupUnits, gu0 = grp * kGroupUnits;
   const uint32_t nu_g = min((uint32_t)kGroupUnits, d.n_units - gu0);
   const uint32_t tiles_g = (nu_g + k_units - 1) / k_units;
+  pub_complete();
   __syncthreads();
-  if (t == 0) {
-    fence_release();
-    *s_flag = (atomicAdd(&d.gctr[grp * kCtrStride], 1u) == tiles_g - 1) ? 1u : 0u;
-  }
+  if (t == 0) *s_flag = (atomicAdd(&d.gctr[grp * kCtrStride], 1u) == tiles_g - 1) ? 1u : 0u;
   __syncthreads();
   if (*s_flag == 0u) return;
-  fence_acquire();
   group_merge(d, grp, gu0, nu_g, s_sig, s_up, s_red);
   if (t == 0) atomicExch(&d.gctr[grp * kCtrStride], 0u);
   // publish the group; the last group merges the instance
+  pub_complete();
   __syncthreads();
-  if (t == 0) {
-    fence_release();
-    *s_flag = (atomicAdd(d.counter, 1u) == d.n_wchunk - 1) ? 1u : 0u;
-  }
+  if (t == 0) *s_flag = (atomicAdd(d.counter, 1u) == d.n_wchunk - 1) ? 1u : 0u;
   __syncthreads();
   if (*s_flag == 0u) return;
-  fence_acquire();
   finalize_instance(d, s_u, s_red, s_trig);   // the inputs' LDS is free: merge scales
   if (t == 0) atomicExch(d.counter, 0u);
 }
@@ -1707,14 +1726,7 @@ void k_rollout(const SolveDesc* __restrict__ descs,
     if (fused)
       tile_epilogue(d, tl.s0, per_tile, s_u, lds_stride, s_J, s_gam, s_mu, s_sig, s_up, s_red, s_trig, &s_flag);
   }
-  if (ctr && threadIdx.x == 0) {
-    fence_release();
-    const uint32_t done = atomicAdd(&ctr->tile_done, 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&ctr->tile_next, 0u);
-      atomicExch(&ctr->tile_done, 0u);
-    }
-  }
+  if (ctr) finish_persistent(&ctr->tile_next, &ctr->tile_done);
 }
 
 constexpr uint32_t kMaxWChunks = BRMPPI_MAX_S / kWChunk;
@@ -1733,9 +1745,12 @@ static_assert(kUnit == 32 && kGroupUnits == 32, "a unit is half a wave; a group'
 // 16-byte load per lane, the 8 rows go through a padded LDS tile of the wave,
 // and lane l then sums unit l % 8 of row l / 8 over its 32 samples in sample
 // order (the weights of its unit are held in registers).  The next 8 rows'
-// loads are in flight meanwhile.  The unit sums are merged in unit order by
-// one thread per row, and the item is published once.  The last block of the
-// instance merges the groups.
+// loads are in flight meanwhile.  A lane keeps its unit sum of every pass in
+// registers; after the last pass they go to LDS, over the tiles, and are
+// merged in unit order by one thread per row; the item is published once.  The
+// last block of the instance merges the groups.  The costs' weights, the
+// tiles, the unit sums and the group scales of the instance merge take turns
+// in one LDS region (under 40 KB a block, so that four blocks share a CU).
 constexpr int kRedRows = 8;                          // rows per wave and pass
 constexpr int kRedUnitStride = kUnit + 4;            // floats per unit segment in the tile (16 B pad)
 constexpr int kRedRowStride = 8 * kRedUnitStride;    // floats per row of a wave's tile
@@ -1873,25 +1888,24 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     if (rg == 0 && t == kWThreads - 1) {   // a thread without a row: overlaps the row merges
       float z, z2;
       group_sums(s_up, s_sig, nu_g, z, z2);
-      d.wpart[grp] = make_float4(s_red[0], z, z2, 0.0f);
+      pub_st4(d.wpart + grp, make_float4(s_red[0], z, z2, 0.0f));
     }
     // group row sums, in unit order
     if (t < nrow) {
       float acc = 0.0f;
       for (uint32_t v = 0; v < nu_g; ++v) acc = unit_row_term(acc, s_sig[v], s_R[t][v]);
-      d.rpart[(size_t)grp * R + r0 + t] = acc;
+      pub_st(d.rpart + (size_t)grp * R + r0 + t, acc);
     }
     // publish: the barrier completes every wave's stores, one release by
     // thread 0 then makes them visible to the block that finishes the instance
+    pub_complete();
     __syncthreads();
     if (t == 0) {
-      fence_release();
       const uint32_t k = atomicAdd(d.counter, 1u);
       s_last = (k == d.n_ritems - 1) ? 1u : 0u;
     }
     __syncthreads();
     if (s_last) {
-      fence_acquire();
       finalize_instance(d, s_scale, s_red, s_trig);
       if (t == 0) atomicExch(d.counter, 0u);
     }
