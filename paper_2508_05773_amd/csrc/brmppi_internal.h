@@ -16,7 +16,8 @@ constexpr int kGroupUnits = 32;              // units per group
 constexpr int kWChunk = kUnit * kGroupUnits; // samples per group
 constexpr int kWThreads = 256;    // threads of the reduce kernel
 constexpr int kRowsPerPass = 8;   // (step, input) rows one pass of the reduce block covers: two per wave
-constexpr int kMaxRowsPerItem = 64;  // rows of one reduce work item (a multiple of kRowsPerPass)
+constexpr int kMaxRowsPerItem = 256; // rows of one reduce work item (a multiple of kRowsPerPass)
+constexpr int kRedBlocksPerCU = 2;   // reduce blocks a CU holds at once (its LDS and registers)
 constexpr size_t kFusedLdsMax = 64 * 1024;   // dynamic LDS bound of the fused rollout
 constexpr uint32_t kCtrStride = 32;          // completion counters one 128-B line apart
 constexpr int kPathWin = 1024;    // waypoints staged in LDS per tile

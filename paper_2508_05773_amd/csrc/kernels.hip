@@ -1765,13 +1765,15 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
   __shared__ float s_R[kMaxRowsPerItem][kGroupUnits + 1];   // +1: row-wise reads hit distinct banks
   __shared__ float4 s_T4[(kWThreads / 64) * kRedRows * kRedRowStride / 4];
   __shared__ float s_red[2 * (kWThreads / 64)];
-  __shared__ float s_scale[kMaxWChunks];
   __shared__ double s_trig[kPlantLds];
   __shared__ uint32_t s_slot, s_last;
   const uint32_t t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   const float* s_gam = reinterpret_cast<const float*>(s_gam4);
   float* s_T = reinterpret_cast<float*>(s_T4) + wid * (kRedRows * kRedRowStride);
+  // the instance merge's group scales use the tiles' LDS (free by then)
+  float* s_scale = reinterpret_cast<float*>(s_T4);
+  static_assert(sizeof(s_T4) >= kMaxWChunks * sizeof(float), "group scales fit the tiles");
   // this lane's place in the wave's tile when storing (sample 4 lane of each
   // row) and when summing (unit lu of row lr)
   const uint32_t st_off = (uint32_t)(lane >> 3) * kRedUnitStride + 4 * (uint32_t)(lane & 7);
@@ -1797,36 +1799,43 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
     const uint32_t nrow = min(d.rows_item, R - r0);
 
     // thread t: samples 4t .. 4t + 3 of the group (unit t / 8); S_pad is a
-    // multiple of 256, so a wave's samples are all inside the buffer or none
+    // multiple of 256, so a wave's samples are all inside the buffer or none.
+    // Every load below is unconditional (a wave past S_pad reads the row's
+    // last 16 bytes and gets weight 0), so that a wait for one pass's rows
+    // can leave the next pass's loads in flight.
     const uint32_t s4 = base + 4 * t;
     const bool sv = s4 < d.S_pad;
-    const float* __restrict__ colp = d.u_star + s4;
-    float4 q[kRedRows];
-    auto load_rows = [&](uint32_t p) {
+    const uint32_t s4c = sv ? s4 : d.S_pad - 4;
+    const float* __restrict__ colp = d.u_star + s4c;
+    // the costs first: waiting for them does not wait for the rows
+    const float4 jc = gld4(reinterpret_cast<const float4*>(d.J + s4c));
+    // two passes of 8 rows in flight: pass p (p / 8 even) in slot 0, the next
+    // in slot 1; a slot is refilled with the pass 16 rows on as soon as its
+    // rows are in the tile.  Rows past nrow repeat the item's last row (cache
+    // hits; their sums are not stored): with no branch around a load, the
+    // wait for one slot never drains the other.
+    float4 q[2][kRedRows];
+    auto load_rows = [&](uint32_t p, auto SLOT) __attribute__((always_inline)) {
+      constexpr int sl = decltype(SLOT)::value;
 #pragma unroll
       for (int j = 0; j < kRedRows; ++j) {
-        const uint32_t rr = p + (uint32_t)j;
+        const uint32_t rr = min(p + (uint32_t)j, nrow - 1);
         // global-space loads: a flat load would also count against the LDS wait
         // counter, and the tile's LDS reads would wait for the next rows' loads
-        q[j] = (sv && rr < nrow) ? gld4(reinterpret_cast<const float4*>(colp + (size_t)(r0 + rr) * d.S_pad))
-                                 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        q[sl][j] = gld4(reinterpret_cast<const float4*>(colp + (size_t)(r0 + rr) * d.S_pad));
       }
     };
-    load_rows(0);    // in flight while the weights are formed
+    using Slot0 = std::integral_constant<int, 0>;
+    using Slot1 = std::integral_constant<int, 1>;
+    load_rows(0u, Slot0{});    // in flight while the weights are formed
+    load_rows((uint32_t)kRedRows, Slot1{});
 
     // costs and unit weights
-    float jv[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    if (sv) {
-      const float4 c = gld4(reinterpret_cast<const float4*>(d.J + s4));
-      jv[0] = c.x;
-      jv[1] = c.y;
-      jv[2] = c.z;
-      jv[3] = c.w;
-    }
+    float jv[4] = {jc.x, jc.y, jc.z, jc.w};
     float m = INFINITY;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (!(s4 + k < S) || !(jv[k] < INFINITY)) jv[k] = INFINITY;  // past S or NaN -> weight 0
+      if (!(s4 + k < S) || !(jv[k] < INFINITY)) jv[k] = INFINITY;  // past S (or S_pad) or NaN -> weight 0
       m = fminf(m, jv[k]);
     }
     m = fminf(m, __shfl_xor(m, 1, 64));
@@ -1865,11 +1874,12 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       }
     }
     // unit row sums, in sample order, 8 rows per pass
-    for (uint32_t p = 0; p < nrow; p += kRedRows) {
+    auto pass = [&](uint32_t p, auto SLOT) __attribute__((always_inline)) {
+      constexpr int sl = decltype(SLOT)::value;
 #pragma unroll
       for (int j = 0; j < kRedRows; ++j)
-        *reinterpret_cast<float4*>(s_T + j * kRedRowStride + st_off) = q[j];
-      load_rows(p + kRedRows);
+        *reinterpret_cast<float4*>(s_T + j * kRedRowStride + st_off) = q[sl][j];
+      load_rows(p + 2 * kRedRows, SLOT);
       __builtin_amdgcn_wave_barrier();
       const float4* u4 = reinterpret_cast<const float4*>(s_T + lr * kRedRowStride + lu * kRedUnitStride);
       float acc = 0.0f;
@@ -1883,6 +1893,10 @@ __global__ __launch_bounds__(kWThreads) void k_reduce(const SolveDesc* __restric
       }
       if (p + lr < nrow) s_R[p + lr][8 * wid + lu] = acc;
       __builtin_amdgcn_wave_barrier();
+    };
+    for (uint32_t p = 0; p < nrow; p += 2 * kRedRows) {
+      pass(p, Slot0{});
+      pass(p + kRedRows, Slot1{});
     }
     __syncthreads();
     if (rg == 0 && t == kWThreads - 1) {   // a thread without a row: overlaps the row merges

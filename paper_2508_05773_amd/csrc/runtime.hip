@@ -180,19 +180,28 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0,
   return L;
 }
 
-// rows of one reduce work item for a launch over these instances: the most
-// rows (fewest barriers and publishes per byte) that still give every CU an
-// item.  Asking for several items per CU (smaller items) was measured slower:
-// the per-item weights, barriers and publish cost more than the finer balance
-// gains.
-uint32_t reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu) {
-  for (uint32_t r = kMaxRowsPerItem; r > kRowsPerPass; r /= 2) {
+// rows of one reduce work item, per instance, for a launch over these
+// instances.  The items of a launch all run at once while there are no more
+// than the reduce blocks the chip holds, so the launch then takes about as
+// long as its longest item: an item gets the fewest passes (of kRowsPerPass
+// rows) that keep the item count within that, and each (instance, group)
+// splits its rows evenly over its items.  Past kMaxRowsPerItem rows per item
+// the items queue up (longest first, see plan_fill).
+void reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu, uint32_t* rows) {
+  const size_t slots = (size_t)std::max(1, n_cu) * kRedBlocksPerCU;
+  const uint32_t max_pp = kMaxRowsPerItem / kRowsPerPass;
+  auto passes = [&](uint32_t i) { return (3 * ps[i]->T + kRowsPerPass - 1) / kRowsPerPass; };
+  uint32_t pp = 1;
+  for (; pp < max_pp; ++pp) {
     size_t items = 0;
     for (uint32_t i = 0; i < n; ++i)
-      items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * ((3 * ps[i]->T + r - 1) / r);
-    if (items >= (size_t)n_cu) return r;
+      items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * ((passes(i) + pp - 1) / pp);
+    if (items <= slots) break;
   }
-  return kRowsPerPass;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t P = passes(i), nrg = (P + pp - 1) / pp;
+    rows[i] = kRowsPerPass * ((P + nrg - 1) / nrg);
+  }
 }
 
 // largest precomputed-noise buffer a plain solve may take; it is also held to
@@ -486,7 +495,9 @@ size_t fused_lds(const brmppi_problem& p, const LaunchShape& sh) {
 
 ScratchLayout plain_layout(const brmppi_ctx* ctx, const brmppi_problem& p, const LaunchShape& sh) {
   const brmppi_problem* pp = &p;
-  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(ctx, p) : 0u, reduce_rows(&pp, 1, ctx->n_cu));
+  uint32_t rows = kRowsPerPass;
+  reduce_rows(&pp, 1, ctx->n_cu, &rows);
+  return scratch_layout(p.S, p.T, variant_pre(sh.variant) ? normals_per_step(ctx, p) : 0u, rows);
 }
 
 hipEvent_t take_event(brmppi_ctx* ctx) {
@@ -726,9 +737,10 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
     }
   }
   size_t n_tiles = 0, n_r = 0;
-  const uint32_t rows_item = reduce_rows(ps, n, ctx->n_cu);
+  std::vector<uint32_t> rows_item(n);
+  reduce_rows(ps, n, ctx->n_cu, rows_item.data());
   for (uint32_t i = 0; i < n; ++i) {
-    bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T, 0, rows_item);
+    bp.layouts[i] = scratch_layout(ps[i]->S, ps[i]->T, 0, rows_item[i]);
     const uint32_t blk = bp.parts[bp.inst_part[i]].block;
     n_tiles += (ps[i]->S + blk - 1) / blk;
     n_r += (size_t)bp.layouts[i].n_wchunk * bp.layouts[i].n_rgroup;
@@ -803,6 +815,14 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
     ++pt.n_tiles;
     bp.tiles.push_back(tc[k].t);
   }
+  // reduce items longest first (stable), for when they outnumber the blocks
+  auto item_rows = [&](const Item& it) {
+    const ScratchLayout& L = bp.layouts[it.inst];
+    const uint32_t r0 = (it.idx % L.n_rgroup) * L.rows_item;
+    return std::min(L.rows_item, 3 * ps[it.inst]->T - r0);
+  };
+  std::stable_sort(bp.ritems.begin(), bp.ritems.end(),
+                   [&](const Item& a, const Item& b) { return item_rows(a) > item_rows(b); });
 }
 
 uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_tiles) {
