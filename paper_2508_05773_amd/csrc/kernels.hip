@@ -1677,11 +1677,17 @@ void k_rollout(const SolveDesc* __restrict__ descs,
       // obstacle row
       s_obs[threadIdx.x] = ObsL{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     }
-    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
-      float4 w = d.path[w0 + j];
-      w.x -= ox;
-      w.y -= oy;
-      s_path[j] = w;
+    // the window's loads all issued before the first store (4 per thread at
+    // 256 threads): one memory latency, not one per waypoint a thread stages
+    for (int j0 = 0; j0 < nw; j0 += 4 * (int)blockDim.x) {
+      float4 w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = d.path[w0 + min(j0 + k * (int)blockDim.x + (int)threadIdx.x, nw - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = j0 + k * (int)blockDim.x + (int)threadIdx.x;
+        if (j < nw) s_path[j] = make_float4(w[k].x - ox, w[k].y - oy, w[k].z, w[k].w);
+      }
     }
     // fused epilogue (direct launch of one instance): LDS for the tile's
     // applied inputs, costs (+inf where no sample stores), weights, units
