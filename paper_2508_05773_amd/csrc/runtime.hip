@@ -181,25 +181,37 @@ ScratchLayout scratch_layout(uint32_t S, uint32_t T, uint32_t noise_normals = 0,
 }
 
 // rows of one reduce work item, per instance, for a launch over these
-// instances.  The items of a launch all run at once while there are no more
-// than the reduce blocks the chip holds, so the launch then takes about as
-// long as its longest item: an item gets the fewest passes (of kRowsPerPass
-// rows) that keep the item count within that, and each (instance, group)
-// splits its rows evenly over its items.  Past kMaxRowsPerItem rows per item
-// the items queue up (longest first, see plan_fill).
+// instances.  An item costs about kRedItemPasses 8-row passes of fixed work
+// (its costs, weights, row merge and publish) plus one per pass of rows, and
+// the reduce blocks the chip holds take the items in rounds, so the launch
+// lasts about (rounds) x (fixed + passes of the longest item).  The passes per
+// item are chosen to minimise that (ties: fewer, longer items), and each
+// (instance, group) splits its rows evenly over its items.  When every item
+// fits one round, the fewest passes that keep it there win; beyond one round
+// longer items cut the fixed work, and plan_fill queues them longest first.
 void reduce_rows(const brmppi_problem* const* ps, uint32_t n, int n_cu, uint32_t* rows) {
+  constexpr uint32_t kRedItemPasses = 5;
   const size_t slots = (size_t)std::max(1, n_cu) * kRedBlocksPerCU;
   const uint32_t max_pp = kMaxRowsPerItem / kRowsPerPass;
   auto passes = [&](uint32_t i) { return (3 * ps[i]->T + kRowsPerPass - 1) / kRowsPerPass; };
-  uint32_t pp = 1;
-  for (; pp < max_pp; ++pp) {
+  uint32_t best_pp = max_pp;
+  size_t best = SIZE_MAX;
+  for (uint32_t pp = 1; pp <= max_pp; ++pp) {
     size_t items = 0;
-    for (uint32_t i = 0; i < n; ++i)
-      items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * ((passes(i) + pp - 1) / pp);
-    if (items <= slots) break;
+    uint32_t longest = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint32_t P = passes(i), nrg = (P + pp - 1) / pp;
+      items += (size_t)((ps[i]->S + kWChunk - 1) / kWChunk) * nrg;
+      longest = std::max(longest, (P + nrg - 1) / nrg);
+    }
+    const size_t cost = ((items + slots - 1) / slots) * (kRedItemPasses + longest);
+    if (cost <= best) {
+      best = cost;
+      best_pp = pp;
+    }
   }
   for (uint32_t i = 0; i < n; ++i) {
-    const uint32_t P = passes(i), nrg = (P + pp - 1) / pp;
+    const uint32_t P = passes(i), nrg = (P + best_pp - 1) / best_pp;
     rows[i] = kRowsPerPass * ((P + nrg - 1) / nrg);
   }
 }
