@@ -1129,13 +1129,20 @@ __device__ __forceinline__ float4 pub_ld4(const float4* p) {
 // moves past it
 __device__ __forceinline__ void pub_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// grab the next work item (persistent) or take blockIdx.x (direct launch)
+// the block's next work item.  Persistent launch (grid <= items): the first
+// item of block b is item b, the later ones come from the queue, past the
+// grid's first round (so that the whole grid does not start on one contended
+// atomic).  Direct launch: item blockIdx.x only.
 __device__ __forceinline__ bool next_item(uint32_t it, uint32_t n_items, uint32_t* ctr_next, uint32_t* s_slot,
                                           uint32_t& ix) {
   if (ctr_next) {
-    if (threadIdx.x == 0) *s_slot = atomicAdd(ctr_next, 1u);
-    __syncthreads();
-    ix = *s_slot;
+    if (it == 0) {
+      ix = blockIdx.x;
+    } else {
+      if (threadIdx.x == 0) *s_slot = gridDim.x + atomicAdd(ctr_next, 1u);
+      __syncthreads();
+      ix = *s_slot;
+    }
   } else {
     if (it > 0) return false;
     ix = blockIdx.x;
@@ -1607,16 +1614,7 @@ void k_rollout(const SolveDesc* __restrict__ descs,
   const uint32_t lds_stride = per_tile + 1;
   for (uint32_t it = 0;; ++it) {
     uint32_t tix;
-    if (ctr) {
-      if (threadIdx.x == 0) s_tile = atomicAdd(&ctr->tile_next, 1u);
-      __syncthreads();
-      tix = s_tile;
-    } else {
-      if (it > 0) break;
-      tix = blockIdx.x;
-    }
-    tix = __builtin_amdgcn_readfirstlane(tix);
-    if (tix >= n_tiles) break;
+    if (!next_item(it, n_tiles, ctr ? &ctr->tile_next : nullptr, &s_tile, tix)) break;
     Tile tl;
     if (tiles) {
       tl = tiles[tix];
