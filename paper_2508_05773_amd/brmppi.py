@@ -274,14 +274,33 @@ def brmppi_solve_ex(ctx, pb: ProblemBuffers, want_J=True, want_useq=False, allow
     return res
 
 
-def brmppi_solve_batch(ctx, pbs: list, allow=(OK,)):
-    n = len(pbs)
-    arr = (brmppi_problem * n)(*[pb.c for pb in pbs])
-    outs = [np.zeros(3 * pb.c.T, np.float32) for pb in pbs]
-    ptrs = (C.POINTER(C.c_float) * n)(*[_fp(o) for o in outs])
-    st = (brmppi_stats * n)()
-    rc = check(lib().brmppi_solve_batch(ctx, arr, n, ptrs, st), allow)
-    return [o.reshape(-1, 3) for o in outs], [_stats_dict(s) for s in st], rc
+class BatchBuffers:
+    """The marshalled arguments of brmppi_solve_batch over a fixed list of
+    problems, reusable across calls: the problem array (a copy of each
+    ProblemBuffers' struct as it is now), one output buffer with a pointer per
+    instance, and the stats array.  The results a call returns are views of
+    the output buffer, which the next call with the same object overwrites."""
+
+    def __init__(self, pbs: list):
+        n = len(pbs)
+        self.pbs = list(pbs)          # keeps the problems' host arrays alive
+        self.n = n
+        self.arr = (brmppi_problem * n)(*[pb.c for pb in pbs])
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum([3 * pb.c.T for pb in pbs])
+        self.out = np.zeros(int(off[-1]), np.float32)
+        base = self.out.ctypes.data
+        self.ptrs = (C.POINTER(C.c_float) * n)(*[C.cast(base + 4 * int(o), C.POINTER(C.c_float)) for o in off[:-1]])
+        self.st = (brmppi_stats * n)()
+        self.views = [self.out[off[i]:off[i + 1]].reshape(-1, 3) for i in range(n)]
+
+
+def brmppi_solve_batch(ctx, pbs, allow=(OK,)):
+    """pbs: a list of ProblemBuffers (marshalled for this call) or a
+    BatchBuffers (marshalled once, reused)."""
+    bb = pbs if isinstance(pbs, BatchBuffers) else BatchBuffers(pbs)
+    rc = check(lib().brmppi_solve_batch(ctx, bb.arr, bb.n, bb.ptrs, bb.st), allow)
+    return bb.views, [_stats_dict(s) for s in bb.st], rc
 
 
 def brmppi_submit(ctx, pb: ProblemBuffers, allow=(OK,)):

@@ -56,6 +56,26 @@ def test_batched_equals_plain(ctx, c3_small):
         B.brmppi_solve(ctx.h, B.ProblemBuffers(c3_small[0], controller=100))
 
 
+def test_batch_buffers_reuse(ctx, c3_small):
+    # arguments marshalled once (BatchBuffers) give the same results as a
+    # list marshalled per call; each call refreshes the returned views
+    log(f"  batch buffers reused over {len(c3_small)} instances")
+    pbs = []
+    for i, p in enumerate(c3_small):
+        ctx.set_path(100 + i, p.path, p.ds)
+        pbs.append(B.ProblemBuffers(p, controller=100 + i))
+    ref, ref_st, _ = B.brmppi_solve_batch(ctx.h, pbs)
+    ref = [r.copy() for r in ref]
+    bb = B.BatchBuffers(pbs)
+    for rep in range(3):
+        bb.out[:] = np.nan
+        outs, st, _ = B.brmppi_solve_batch(ctx.h, bb)
+        for i in range(len(c3_small)):
+            assert np.array_equal(outs[i], ref[i]), (rep, i)
+            assert np.shares_memory(outs[i], bb.out), i
+            assert st[i]["Z"] == ref_st[i]["Z"], (rep, i)
+
+
 def test_batched_matches_oracle(ctx, c3_small):
     from oracle import oracle as O
     pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(c3_small)]
