@@ -1741,20 +1741,18 @@ static_assert(kUnit == 32 && kGroupUnits == 32, "a unit is half a wave; a group'
 
 // Reduction from the applied inputs in HBM (batched launches and tiles that
 // are not whole units), with the same canonical structure as the fused
-// epilogue.  Work item = (group of 1024 samples, d.rows_item rows): the
-// group's unit weights are recomputed from its 4 KB of costs (same code: same
-// values), the first row block also stores the group's (m_g, Z_g, Z2_g).
-// Wave w owns the group's samples 256 w .. 256 w + 255 (units 8 w .. 8 w + 7)
-// and takes the item's rows 8 at a time: each row is read with one coalesced
-// 16-byte load per lane, the 8 rows go through a padded LDS tile of the wave,
-// and lane l then sums unit l % 8 of row l / 8 over its 32 samples in sample
-// order (the weights of its unit are held in registers).  The next 8 rows'
-// loads are in flight meanwhile.  A lane keeps its unit sum of every pass in
-// registers; after the last pass they go to LDS, over the tiles, and are
-// merged in unit order by one thread per row; the item is published once.  The
-// last block of the instance merges the groups.  The costs' weights, the
-// tiles, the unit sums and the group scales of the instance merge take turns
-// in one LDS region (under 40 KB a block, so that four blocks share a CU).
+// epilogue.  Work item = (group of 1024 samples, d.rows_item rows, up to
+// 256): the group's unit weights are recomputed from its 4 KB of costs (same
+// code: same values), the first row block also stores the group's (m_g, Z_g,
+// Z2_g).  Wave w owns the group's samples 256 w .. 256 w + 255 (units 8 w ..
+// 8 w + 7) and takes the item's rows 8 at a time: each row is read with one
+// coalesced 16-byte load per lane, the 8 rows go through a padded LDS tile of
+// the wave, and lane l then sums unit l % 8 of row l / 8 over its 32 samples
+// in sample order (the weights of its unit are held in registers).  The next
+// two passes' loads are in flight meanwhile.  The unit sums go to LDS and are
+// merged in unit order by one thread per row; the item is published once.
+// The last block of the instance merges the groups, with the group scales in
+// the tiles' LDS.  Two blocks share a CU (LDS).
 constexpr int kRedRows = 8;                          // rows per wave and pass
 constexpr int kRedUnitStride = kUnit + 4;            // floats per unit segment in the tile (16 B pad)
 constexpr int kRedRowStride = 8 * kRedUnitStride;    // floats per row of a wave's tile
