@@ -117,3 +117,24 @@ def test_default_params_without_a_device():
     assert B.lib().brmppi_default_params(None) == B.EINVAL
     assert B.lib().brmppi_set_params(None, 0, None) == B.EINVAL
     assert B.lib().brmppi_get_info(None, None) == B.EINVAL
+
+
+def test_batch_buffers_layout():
+    # BatchBuffers: one output buffer, a pointer per instance at its offset,
+    # views of 3T floats each, and the problem array copied from the structs
+    from paper_2508_05773_amd import workloads as W
+
+    insts = W.config3(n_instances=5, seed=1)
+    pbs = [B.ProblemBuffers(p, controller=i) for i, p in enumerate(insts)]
+    bb = B.BatchBuffers(pbs)
+    assert bb.n == 5 and bb.out.size == sum(3 * p.T for p in insts)
+    base = bb.out.ctypes.data
+    off = 0
+    for i, p in enumerate(insts):
+        assert C.cast(bb.ptrs[i], C.c_void_p).value == base + 4 * off, i
+        assert bb.views[i].shape == (p.T, 3)
+        assert np.shares_memory(bb.views[i], bb.out)
+        bb.views[i][:] = i
+        off += 3 * p.T
+        assert bb.arr[i].S == p.S and bb.arr[i].T == p.T and bb.arr[i].controller == i
+    assert np.array_equal(np.unique(bb.out), np.arange(5, dtype=np.float32))
