@@ -70,7 +70,7 @@ def test_reduce_kernel_repeats_bitwise(ctx, block, variant):
 
 
 def test_batched_reduce_repeats_bitwise(ctx):
-    insts = W.config3(n_instances=40, seed=7)
+    insts = W.config3()     # 64 uneven instances: reduce items of up to 136 rows
     log(f"  batched: {len(insts)} uneven instances, 40 repeats (graph replays)")
     pbs = []
     for i, p in enumerate(insts):
@@ -82,6 +82,10 @@ def test_batched_reduce_repeats_bitwise(ctx):
         for i in range(len(insts)):
             assert np.array_equal(outs[i], outs0[i]), (k, i)
             assert st[i]["Z"] == st0[i]["Z"], (k, i)
+    # the batch's long reduce items give the bits of plain solves
+    for i in range(0, len(insts), 5):
+        u, _, _ = B.brmppi_solve(ctx.h, pbs[i])
+        assert np.array_equal(u, outs0[i]), i
 
 
 def test_batched_reduce_several_rounds(ctx):
