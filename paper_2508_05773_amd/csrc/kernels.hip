@@ -1536,8 +1536,7 @@ constexpr int rollout_waves_per_simd() {
 }
 
 // Inlined into the kernel: as a function call, every lane saved and restored
-// its callee-saved registers around it (tens of bytes of scratch per lane,
-// written back to HBM by the publish fences).
+// its callee-saved registers around it (tens of bytes of scratch per lane).
 __device__ __forceinline__ void tile_epilogue(const SolveDesc& d, uint32_t s0, uint32_t per_tile, float* s_u, uint32_t lds_stride,
                               const float* s_J, float* s_gam, float* s_mu, float* s_sig, float4* s_up,
                               float* s_red, double* s_trig, uint32_t* s_flag) {
