@@ -312,8 +312,14 @@ def batched_leg(B, W, ctx):
         B.brmppi_solve_batch(h, bb)
     t_batch = (time.perf_counter() - t0) / reps_b
     ss = sum(p.S * p.T for p in insts)
+    # algorithmic flops of the batch (one-lane rollouts, noise drawn in the
+    # kernel) over the whole call's time: a lower bound on the rollout's rate
+    fl = sum(rollout_flops(p.S, p.T, p.n_obs, hitch=not (p.flags & W.FLAG_HITCH_OFF),
+                           guided=not (p.flags & W.FLAG_GUIDANCE_OFF)) for p in insts)
     return {
         "workload": "64 uneven instances: S in {1024..16384}, T in [20, 80], 0-16 obstacles",
+        "tflops": fl / t_batch / 1e12, "frac": fl / t_batch / 1e12 / PEAK_FP32_TFLOPS,
+        "frac_nonpacked": fl / t_batch / 1e12 / PEAK_FP32_NONPACKED_TFLOPS,
         "instances": len(insts), "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
         "plain_solves_per_s": len(insts) / t_plain, "batched_solves_per_s": len(insts) / t_batch,
         "speedup": t_plain / t_batch, "batched_sample_steps_per_s": ss / t_batch,
@@ -392,7 +398,8 @@ def served_replay(args, B, W, ctx, ctrls, n_active, seconds, base_id=300):
     """Real-time replay of the arrival process of the first n_active controllers
     (one request per 10 ms tick each, Exp(1 ms) jitter, a random phase), served
     by continuous batching; every controller runs its closed loop on the device.
-    Returns the solves, the sample-steps and the latency of every request
+    Returns the solves, the sample-steps, the algorithmic flops (one-lane
+    rollouts, noise drawn in the kernel) and the latency of every request
     (submit to result ready, the library's clock)."""
     h = ctx.h
     pbs = []
@@ -405,14 +412,15 @@ def served_replay(args, B, W, ctx, ctrls, n_active, seconds, base_id=300):
                     B.ProblemBuffers(p, controller=base_id + c, with_nominal=False, flags=flags)])
     events = W.config4_arrivals(n_active, seconds)
     started = [False] * n_active
-    outstanding = []          # (ticket, T, sample-steps)
+    outstanding = []          # (ticket, T, sample-steps, flops)
     lat = []
     ss_total = 0
+    fl_total = 0.0
     t_start = time.perf_counter()
 
     def take(block):
-        nonlocal ss_total
-        t, T, ssk = outstanding[0]
+        nonlocal ss_total, fl_total
+        t, T, ssk, flk = outstanding[0]
         if block:
             u, st, rc = B.brmppi_wait(h, t, T, timeout_ms=120000, allow=(B.OK, B.ENONFINITE))
         else:
@@ -422,6 +430,7 @@ def served_replay(args, B, W, ctx, ctrls, n_active, seconds, base_id=300):
         outstanding.pop(0)
         lat.append(st["latency_us"] * 1e-3)
         ss_total += ssk
+        fl_total += flk
         return True
 
     for (te, c, k) in events:
@@ -436,19 +445,20 @@ def served_replay(args, B, W, ctx, ctrls, n_active, seconds, base_id=300):
                 break
             take(True)        # back-pressure: the queue is full, wait for the oldest request
         started[c] = True
-        outstanding.append((t, pb.c.T, pb.c.S * pb.c.T))
+        p = ctrls[c]
+        outstanding.append((t, pb.c.T, pb.c.S * pb.c.T, rollout_flops(p.S, p.T, p.n_obs)))
         while outstanding and take(False):
             pass
     while outstanding:
         take(True)
     wall = time.perf_counter() - t_start
-    return events, pbs, lat, ss_total, wall
+    return events, pbs, lat, ss_total, fl_total, wall
 
 
 def served_leg(args, B, W, ctx):
     ctrls = W.config4_controllers()
     n = len(ctrls)
-    events, pbs, lat, ss_total, wall = served_replay(args, B, W, ctx, ctrls, n, args.served_seconds)
+    events, pbs, lat, ss_total, fl_total, wall = served_replay(args, B, W, ctx, ctrls, n, args.served_seconds)
     done = len(lat)
     # sequential plain solves of the same kind of requests (first 512 events)
     seq_events = events[:512]
@@ -462,6 +472,10 @@ def served_leg(args, B, W, ctx):
         "simulated_s": args.served_seconds, "requests": len(events), "wall_s": wall,
         "offered_per_s": len(events) / args.served_seconds,
         "solves_per_s": done / wall, "sample_steps_per_s": ss_total / wall,
+        # algorithmic flops of the completed requests over the wall time (host
+        # and reduce included): a lower bound on the rollouts' own rate
+        "tflops": fl_total / wall / 1e12, "frac": fl_total / wall / 1e12 / PEAK_FP32_TFLOPS,
+        "frac_nonpacked": fl_total / wall / 1e12 / PEAK_FP32_NONPACKED_TFLOPS,
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
         "sequential_plain_solves_per_s": len(seq_events) / t_seq,
         "speedup_vs_sequential": (done / wall) / (len(seq_events) / t_seq),
@@ -470,7 +484,7 @@ def served_leg(args, B, W, ctx):
     # n x 100 requests/s); the highest load whose p99 stays under the 10 ms tick
     sweep = []
     for n_active in [int(x) for x in args.served_sweep.split(",") if x]:
-        ev, _, lt, ss, wl = served_replay(args, B, W, ctx, ctrls, min(n_active, n), args.sweep_seconds)
+        ev, _, lt, ss, _, wl = served_replay(args, B, W, ctx, ctrls, min(n_active, n), args.sweep_seconds)
         sweep.append({"controllers": min(n_active, n), "offered_per_s": len(ev) / args.sweep_seconds,
                       "solves_per_s": len(lt) / wl, "p50_ms": pct(lt, 50), "p99_ms": pct(lt, 99),
                       "max_ms": float(np.max(lt)) if lt else None, "sample_steps_per_s": ss / wl})
@@ -482,7 +496,7 @@ def served_leg(args, B, W, ctx):
     out["max_load_p99_under_tick"] = best
     # that load held for the 5 s the served workload specifies
     if best is not None and args.sustain_seconds > 0:
-        ev, _, lt, ss, wl = served_replay(args, B, W, ctx, ctrls, best["controllers"], args.sustain_seconds)
+        ev, _, lt, ss, _, wl = served_replay(args, B, W, ctx, ctrls, best["controllers"], args.sustain_seconds)
         out["sustained"] = {"controllers": best["controllers"], "seconds": args.sustain_seconds,
                             "requests": len(ev), "offered_per_s": len(ev) / args.sustain_seconds,
                             "solves_per_s": len(lt) / wl, "p50_ms": pct(lt, 50), "p99_ms": pct(lt, 99),
