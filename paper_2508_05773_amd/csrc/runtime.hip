@@ -307,6 +307,8 @@ struct brmppi_ctx {
   uint64_t scratch_grows = 0;
   Pinned pin;                   // blocking staging
   hipEvent_t loop_ev[2] = {nullptr, nullptr};   // closed loop: completion of each staging half
+  // the last batched solve's plan (type-erased: defined with the batch code)
+  std::shared_ptr<void> plan_cache;
   // graph cache for the batched form
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -791,8 +793,22 @@ void plan_layout(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, B
   bp.total = o;
 }
 
-void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, char* base, BatchPlan& bp) {
+// the descriptors of a batch (every call: they hold its inputs)
+void plan_descs(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, char* base, BatchPlan& bp) {
   bp.descs.resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const brmppi_problem& p = *ps[i];
+    const float* unom_dev = p.u_nom ? reinterpret_cast<const float*>(base + bp.unom_off[i]) : nullptr;
+    uint32_t* counter = reinterpret_cast<uint32_t*>(base + bp.off_counters) + i;
+    float* out = reinterpret_cast<float*>(base + bp.off_outs) + bp.out_pos[i];
+    fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0, unom_dev,
+              counter, out);
+  }
+}
+
+// the tiles and reduce items of a batch, in launch order (they depend only on
+// its composition: see batch_signature)
+void plan_work(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, BatchPlan& bp) {
   bp.tiles.clear();
   bp.ritems.clear();
   struct TC {
@@ -803,11 +819,6 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
   std::vector<TC> tc;
   for (uint32_t i = 0; i < n; ++i) {
     const brmppi_problem& p = *ps[i];
-    const float* unom_dev = p.u_nom ? reinterpret_cast<const float*>(base + bp.unom_off[i]) : nullptr;
-    uint32_t* counter = reinterpret_cast<uint32_t*>(base + bp.off_counters) + i;
-    float* out = reinterpret_cast<float*>(base + bp.off_outs) + bp.out_pos[i];
-    fill_desc(bp.descs[i], p, ctx->ctrl[p.controller], bp.layouts[i], base + bp.scratch_off[i], 0, unom_dev,
-              counter, out);
     // guidance-off instances inside a guided batch: the flag is honoured per tile
     const double cost = (double)p.T * (10.0 + ((p.flags & BRMPPI_GUIDANCE_OFF) ? 0.0 : 2.0 + obstacle_rows(ctx, p)));
     const uint32_t pi = bp.inst_part[i], blk = bp.parts[pi].block;
@@ -835,6 +846,41 @@ void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, cha
   };
   std::stable_sort(bp.ritems.begin(), bp.ritems.end(),
                    [&](const Item& a, const Item& b) { return item_rows(a) > item_rows(b); });
+}
+
+void plan_fill(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, char* base, BatchPlan& bp) {
+  plan_descs(ctx, ps, n, base, bp);
+  plan_work(ctx, ps, n, bp);
+}
+
+// What plan_layout and plan_work depend on: the launch table and, per
+// instance, S, T, the constraint rows, the flags and whether a nominal
+// sequence comes with the call.  A batched solve with the signature of the
+// previous one reuses its layout, tiles and reduce items (a control loop
+// that re-solves the same set of problems every tick), and only refills the
+// descriptors.
+void batch_signature(brmppi_ctx* ctx, const brmppi_problem* const* ps, uint32_t n, std::vector<uint64_t>& sig) {
+  sig.clear();
+  sig.reserve(8 + 3 * (size_t)n);
+  sig.push_back(n);
+  sig.push_back(ctx->forced.block);
+  for (uint32_t b : ctx->batch_block) sig.push_back(b);
+  for (uint32_t i = 0; i < n; ++i) {
+    sig.push_back(((uint64_t)ps[i]->S << 32) | ps[i]->T);
+    sig.push_back(((uint64_t)obstacle_rows(ctx, *ps[i]) << 32) | ps[i]->flags);
+    sig.push_back(ps[i]->u_nom ? 1u : 0u);
+  }
+}
+
+struct BatchPlanCache {
+  std::vector<uint64_t> sig;   // empty: no valid plan
+  BatchPlan bp;
+};
+
+BatchPlanCache& plan_cache(brmppi_ctx* ctx) {
+  if (!ctx->plan_cache)
+    ctx->plan_cache = std::shared_ptr<void>(new BatchPlanCache, [](void* q) { delete static_cast<BatchPlanCache*>(q); });
+  return *static_cast<BatchPlanCache*>(ctx->plan_cache.get());
 }
 
 uint32_t persistent_grid(brmppi_ctx* ctx, int bucket, uint32_t block, size_t n_tiles) {
@@ -947,12 +993,24 @@ int solve_batch_locked(brmppi_ctx* ctx, const brmppi_problem* probs, uint32_t n,
     seen[probs[i].controller] = 1;
     ps[i] = &probs[i];
   }
-  BatchPlan bp;
-  plan_layout(ctx, ps.data(), n, bp);
+  BatchPlanCache& pc = plan_cache(ctx);
+  std::vector<uint64_t> sig;
+  batch_signature(ctx, ps.data(), n, sig);
+  const bool same = !pc.sig.empty() && sig == pc.sig;
+  if (!same) {
+    pc.sig.clear();
+    pc.bp = BatchPlan{};
+    plan_layout(ctx, ps.data(), n, pc.bp);
+  }
+  BatchPlan& bp = pc.bp;
   int rc;
   if ((rc = ensure_scratch(ctx, bp.total))) return rc;
   char* base = ctx->scratch.ptr;
-  plan_fill(ctx, ps.data(), n, base, bp);
+  plan_descs(ctx, ps.data(), n, base, bp);
+  if (!same) {
+    plan_work(ctx, ps.data(), n, bp);
+    pc.sig = std::move(sig);
+  }
   hipStream_t s = ctx->streams[0];
   if ((rc = ctx->pin.ensure(bp.header_bytes + bp.out_floats * sizeof(float)))) return rc;
   char* pin = ctx->pin.ptr;

@@ -76,6 +76,34 @@ def test_batch_buffers_reuse(ctx, c3_small):
             assert st[i]["Z"] == ref_st[i]["Z"], (rep, i)
 
 
+def test_batch_plan_reuse(ctx, c3_small):
+    # a batch with the previous one's composition reuses its plan (layout,
+    # tiles, reduce items) and refills only the descriptors: new seeds and
+    # states must give the plain solves' results; a changed composition
+    # plans afresh
+    log(f"  batch plan reuse over {len(c3_small)} instances")
+    for i, p in enumerate(c3_small):
+        ctx.set_path(100 + i, p.path, p.ds)
+
+    def check(probs, tag):
+        pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(probs)]
+        outs, _, _ = B.brmppi_solve_batch(ctx.h, pbs)
+        for i, pb in enumerate(pbs):
+            u, _, _ = B.brmppi_solve(ctx.h, pb)
+            assert np.array_equal(outs[i], u), (tag, i)
+
+    base = list(c3_small)
+    check(base, "first")
+    # same composition, other contents: seeds and start states
+    moved = [p.copy(seed=p.seed + 17, x0=p.x0 + np.float32(0.05)) for p in base]
+    check(moved, "same composition")
+    # another composition (one horizon changed), then the first again
+    other = list(base)
+    other[3] = other[3].copy(T=other[3].T + 4, u_nom=np.zeros((other[3].T + 4, 3), np.float32))
+    check(other, "changed composition")
+    check(base, "first again")
+
+
 def test_batched_matches_oracle(ctx, c3_small):
     from oracle import oracle as O
     pbs = [B.ProblemBuffers(p, controller=100 + i) for i, p in enumerate(c3_small)]
