@@ -520,8 +520,11 @@ hipEvent_t take_event(brmppi_ctx* ctx) {
     ctx->ev_pool.pop_back();
     return e;
   }
+  // timing only (read after a stream sync): no system-scope fence at the
+  // record, whose cache write-back and invalidation would otherwise land in
+  // the measured interval and slow the next kernel
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
