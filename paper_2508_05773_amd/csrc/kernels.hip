@@ -170,7 +170,7 @@ struct RefPoint {
 // Reference zeta(psi): linear interpolation between waypoints, headings by the
 // wrapped difference, clamped to the ends.  f = phi0 + psi_rel/ds is the
 // fractional waypoint index relative to k0.
-template <bool GLB>
+template <bool GLB, bool SPLIT = false>
 __device__ __forceinline__ RefPoint reference(float f, int k0, int n_path, const float4* __restrict__ spath,
                                               int w0, int nw, const float4* __restrict__ gpath, float ox,
                                               float oy) {
@@ -188,10 +188,29 @@ __device__ __forceinline__ RefPoint reference(float f, int k0, int n_path, const
   if (!(t >= 0.0f)) t = 0.0f;
   const int li = gi - w0;
   float4 A, B;
-  if constexpr (GLB) {
+  if constexpr (GLB && SPLIT) {
     // the window in LDS serves every lane unless one leaves it: then (a
-    // wave-uniform, rare case) each lane reads its point from LDS or HBM
-    // through a generic pointer
+    // wave-uniform, rare case) the lanes outside read their points from HBM.
+    // LDS is read through the local address space and HBM through the global
+    // one, each consumed on its own side of the branch: no flat access, whose
+    // wait would also drain the step-ahead HBM loads in flight.
+    const int lc = min(max(li, 0), nw - 2);
+    const bool outside = !(li >= 0 && li + 1 < nw);
+    A = lds(spath + lc);
+    B = lds(spath + lc + 1);
+    if (__any(outside)) {
+      const float4 Ag = gld4(gpath + gi), Bg = gld4(gpath + gi + 1);
+      A.x = outside ? Ag.x - ox : A.x;
+      A.y = outside ? Ag.y - oy : A.y;
+      A.z = outside ? Ag.z : A.z;
+      A.w = outside ? Ag.w : A.w;
+      B.x = outside ? Bg.x - ox : B.x;
+      B.y = outside ? Bg.y - oy : B.y;
+      B.z = outside ? Bg.z : B.z;
+      B.w = outside ? Bg.w : B.w;
+    }
+  } else if constexpr (GLB) {
+    // the same through a generic pointer (the eight-lane form's choice)
     const int lc = min(max(li, 0), nw - 2);
     const bool outside = !(li >= 0 && li + 1 < nw);
     if (__any(outside)) {
@@ -699,8 +718,8 @@ __device__ __forceinline__ float lane_value(float x) {
 template <int NOB, bool GUIDED, int G, bool PRE, bool E4, bool DISC>
 __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, bool store, int g, const float* x0,
                                                const ObsL* __restrict__ sobs, const float4* __restrict__ spath,
-                                               int w0, int nw, int k0, float phi0, float* s_u, uint32_t lds_stride,
-                                               uint32_t t_local, float* s_J) {
+                                               const float* __restrict__ s_un, int w0, int nw, int k0, float phi0,
+                                               float* s_u, uint32_t lds_stride, uint32_t t_local, float* s_J) {
   static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lanes per sample");
   static_assert(PRE || G == 1, "a sample shared by lanes reads precomputed normals");
   constexpr int NSL = GUIDED ? (NOB + G - 1) / G : 1;   // obstacle slots of this lane
@@ -748,11 +767,19 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   const uint32_t S_pad = d.S_pad;
   float* __restrict__ ustar = d.u_star;
   const float* __restrict__ unom = d.u_nom_in;
-  // With eight lanes per sample (the form for few samples, where one wave per
-  // SIMD leaves every latency exposed) the next step's nominal inputs are
-  // fetched one step ahead, off the dependency chain of the step.
-  constexpr bool kAhead = (G == 8);
   constexpr bool kGlb = (G > 1);
+  // Two arrangements of the step's memory accesses, each the faster for its
+  // forms (measured):
+  // - eight lanes per sample (few samples: one wave per SIMD, every latency
+  //   exposed, the schedule of the step's chain what counts): the next step's
+  //   nominal inputs fetched from HBM one step ahead, the normals' queue slot
+  //   refilled as soon as it is read;
+  // - the others (several waves per SIMD, memory waits what counts): the
+  //   nominal inputs read from LDS (staged with the tile), the slot refilled
+  //   after the last use of its values, whole pairs of steps per pass of the
+  //   loop, the reference window read without flat accesses.
+  constexpr bool kAhead = (G == 8);
+  constexpr bool kLate = PRE && !kAhead;
   // Stage costs.  One lane per sample evaluates the cost of every step.  With
   // G > 1 lanes the cost is not repeated on every lane: lane g keeps the cost
   // inputs of the steps tau with tau % G == g (state, progress and applied
@@ -762,9 +789,14 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // one-lane form, and only lane 0 (the lane that stores) holds it.
   constexpr bool kBatchCost = (G > 1);
   RefPoint rf{};
-  if constexpr (!kBatchCost) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  if constexpr (!kBatchCost) rf = reference<kGlb, !kAhead>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float k_px = 0.0f, k_py = 0.0f, k_th1 = 0.0f, k_th2 = 0.0f, k_psi = 0.0f, k_uj = 0.0f, k_uw = 0.0f, k_unu = 0.0f;
-  float un_j = ldf<kGlb>(unom + 0), un_w = ldf<kGlb>(unom + 1), un_nu = ldf<kGlb>(unom + 2);
+  float un_j = 0.0f, un_w = 0.0f, un_nu = 0.0f;
+  if constexpr (kAhead) {
+    un_j = ldf<kGlb>(unom + 0);
+    un_w = ldf<kGlb>(unom + 1);
+    un_nu = ldf<kGlb>(unom + 2);
+  }
   // the hitch rows are owned by lanes 0 and 1; the others zero their copy by
   // this factor (c = 0 makes every term of the row's sums an exact zero)
   const float hz_own = (hitch && g < 2) ? 1.0f : 0.0f;
@@ -795,8 +827,11 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     }
   };
   if constexpr (PRE) {
+    // (kLate: slot 0 before slot 1, in this order, as inside the loop)
     load_normals(0u, 0);
+    if constexpr (kLate) __builtin_amdgcn_sched_barrier(0);
     load_normals(min(1u, d.T - 1), 1);
+    if constexpr (kLate) __builtin_amdgcn_sched_barrier(0);
   }
 
   auto step = [&](const uint32_t tau, auto SLOT) __attribute__((always_inline)) {
@@ -811,7 +846,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       for (int k = 0; k < NH; ++k) e_h[k] = nx_h[q][k];
 #pragma unroll
       for (int j = 0; j < NSL; ++j) e_o[j] = nx_o[q][j];
-      load_normals(min(tau + 2, d.T - 1), q);
+      if constexpr (!kLate) load_normals(min(tau + 2, d.T - 1), q);
     } else {
       float eps[4 * NBMAX];
 #pragma unroll
@@ -831,23 +866,35 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
         for (int j = 0; j < NSL; ++j) e_o[j] = eps[5 + j];   // G == 1: slot j is obstacle j
       }
     }
-    if constexpr (!kAhead) {
-      un_j = ldf<kGlb>(unom + 3 * tau + 0);
-      un_w = ldf<kGlb>(unom + 3 * tau + 1);
-      un_nu = ldf<kGlb>(unom + 3 * tau + 2);
-    }
-    float uj = un_j + P.sigma_j * e_in[0];
-    float uw = un_w + P.sigma_w * e_in[1];
-    const float unu = un_nu + P.sigma_nu * e_in[2];
+    float uj, uw, unu;
     if constexpr (kAhead) {
+      uj = un_j + P.sigma_j * e_in[0];
+      uw = un_w + P.sigma_w * e_in[1];
+      unu = un_nu + P.sigma_nu * e_in[2];
       const uint32_t tn = min(tau + 1, d.T - 1);
       un_j = ldf<kGlb>(unom + 3 * tn + 0);
       un_w = ldf<kGlb>(unom + 3 * tn + 1);
       un_nu = ldf<kGlb>(unom + 3 * tn + 2);
+    } else {
+      // staged in LDS with the tile: a broadcast read, no HBM load to keep in
+      // flight across the loop's back edge
+      uj = lds(s_un + 3 * tau + 0) + P.sigma_j * e_in[0];
+      uw = lds(s_un + 3 * tau + 1) + P.sigma_w * e_in[1];
+      unu = lds(s_un + 3 * tau + 2) + P.sigma_nu * e_in[2];
+    }
+    // the rows' auxiliary-input perturbations: with the inputs' above, the
+    // only uses of the step's normals (kLate: formed here, before the refill;
+    // otherwise in the rows)
+    float at_h[NH], at_o[NSL];
+    if constexpr (GUIDED && kLate) {
+#pragma unroll
+      for (int k = 0; k < NH; ++k) at_h[k] = P.sigma_a * e_h[k];
+#pragma unroll
+      for (int j = 0; j < NSL; ++j) at_o[j] = P.sigma_a * e_o[j];
     }
     const float psi_next = psi + Ts * unu;
     if constexpr (!kBatchCost) {
-      if (tau > 0) rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      if (tau > 0) rf = reference<kGlb, !kAhead>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
     }
     // (the fourth angle, the reference heading, only for the per-step cost)
     const StepTrig tg = step_trig<G>(g, th1, th1 - th2, dl, kBatchCost ? dl : rf.th1);
@@ -856,6 +903,23 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     const float kd = tn * inv_l1;     // th1_dot = v kd
     const float vkd = v * kd;
     const float Aw2 = sp - ch * cp * tn;
+    // Refill the queue slot with step tau + 2 only now, after the last use of
+    // its values (the trigonometry above covers the nominal inputs' LDS
+    // read): a refill hoisted above a use needs a second register, and the
+    // copy back into the slot's register at the loop's back edge would wait
+    // for every load in flight (the prefetch lost).  The empty asm pins the
+    // normals' products here (the compiler would otherwise sink them to their
+    // uses in the rows, past the refill) and the scheduling barrier keeps the
+    // refill below them.
+    if constexpr (kLate) {
+      asm volatile("" : "+v"(uj), "+v"(uw), "+v"(unu));
+#pragma unroll
+      for (int k = 0; k < NH; ++k) asm volatile("" : "+v"(at_h[k]));
+#pragma unroll
+      for (int j = 0; j < NSL; ++j) asm volatile("" : "+v"(at_o[j]));
+      __builtin_amdgcn_sched_barrier(0);
+      load_normals(min(tau + 2, d.T - 1), q);
+    }
 
     if (GUIDED && guided) {
       const float sec2 = 1.0f + tn * tn;
@@ -881,7 +945,8 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           const float hd = -P.kappa * a - sg * D;
           const float hv = -P.kappa - sg * Ts * D_v;
           const float Lf = Ts * (hv * a - sg * (1.0f - Ts * D_phi) * D);
-          H[k] = row_terms(K, h + Ts * hd, Lf, -P.kappa * Ts2, -sg * Ts2 * D_dl, P.sigma_a * e_h[k], alpha_h[k]);
+          H[k] = row_terms(K, h + Ts * hd, Lf, -P.kappa * Ts2, -sg * Ts2 * D_dl,
+                         kLate ? at_h[k] : P.sigma_a * e_h[k], alpha_h[k]);
         }
       }
       // rows of virtual lane g + G i: its hitch row, then obstacles in order
@@ -906,7 +971,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
           if constexpr (G == 1) {
             if (o < n_obs) {
               const ObsRow R = obstacle_row_sel<E4, DISC>(sobs[o], DB, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
-              O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+              O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, kLate ? at_o[j] : P.sigma_a * e_o[j], alpha_o[j]);
               acc_row(A, O[j]);
             }
           } else if (G * j < n_obs) {
@@ -914,7 +979,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
             // 0): its row has hhat = -1 and Lf = g = +-0, so it adds exact
             // zeros to the sums, without a divergent branch or selects
             const ObsRow R = obstacle_row_sel<E4, DISC>(sobs[o], DB, px, py, v, a, c1, s1, vkd, sec2, t, Ts, Ts2, inv_l1);
-            O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, P.sigma_a * e_o[j], alpha_o[j]);
+            O[j] = row_terms(K, R.hhat, R.Lf, R.g0, R.g1, kLate ? at_o[j] : P.sigma_a * e_o[j], alpha_o[j]);
             acc_row(A, O[j]);
           }
         }
@@ -996,7 +1061,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   // costs of the kept steps tau0 .. tau0 + n - 1 (lane g: step tau0 + g)
   auto flush_costs = [&](uint32_t tau0, uint32_t n) __attribute__((always_inline)) {
     if constexpr (kBatchCost) {
-      const RefPoint r = reference<kGlb>(phi0 + k_psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+      const RefPoint r = reference<kGlb, !kAhead>(phi0 + k_psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
       float sr, cr;
       step_sincos(r.th1, &sr, &cr);
       float rc = stage_cost(P, r, sr, cr, k_px, k_py, k_th1, k_th2, k_uj, k_uw, k_unu);
@@ -1022,7 +1087,22 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
       if (((tau + 1) & (G - 1)) == 0 || tau + 1 == d.T) flush_costs(tau & ~(uint32_t)(G - 1), (tau & (G - 1)) + 1);
     }
   };
-  if constexpr (PRE) {
+  if constexpr (kLate) {
+    // whole pairs, then an odd last step: every pass of the loop issues both
+    // slots' refills, so a step's wait for its own slot leaves the other
+    // slot's loads in flight
+    uint32_t tau = 0;
+    for (; tau + 1 < d.T; tau += 2) {
+      step(tau, std::integral_constant<int, 0>{});
+      after_step(tau);
+      step(tau + 1, std::integral_constant<int, 1>{});
+      after_step(tau + 1);
+    }
+    if (tau < d.T) {
+      step(tau, std::integral_constant<int, 0>{});
+      after_step(tau);
+    }
+  } else if constexpr (PRE) {
     for (uint32_t tau = 0; tau < d.T; tau += 2) {
       step(tau, std::integral_constant<int, 0>{});
       after_step(tau);
@@ -1034,7 +1114,7 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   } else {
     for (uint32_t tau = 0; tau < d.T; ++tau) step(tau, std::integral_constant<int, 0>{});
   }
-  rf = reference<kGlb>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
+  rf = reference<kGlb, !kAhead>(phi0 + psi * inv_ds, k0, n_path, spath, w0, nw, gpath, ox, oy);
   float rN = tracking_cost(P, rf, px, py, th1, th2);   // rf: the reference at psi_T
   if (penalty) rN += P.w_col * collision_pen<E4, DISC>(sobs, n_obs, px, py, th1, th2, t0 + (float)d.T * Ts);
   J += (double)rN;
@@ -1604,6 +1684,7 @@ void k_rollout(const SolveDesc* __restrict__ descs,
                                                        const Tile* __restrict__ tiles, uint32_t n_tiles,
                                                        BatchCounters* __restrict__ ctr) {
   __shared__ float4 s_path[kPathWin];
+  __shared__ float s_unom[3 * BRMPPI_MAX_T];
   __shared__ ObsL s_obs[BRMPPI_MAX_OBS];
   __shared__ uint32_t s_tile, s_flag;
   __shared__ float s_red[2 * (kMaxBlock / 64)];
@@ -1674,8 +1755,16 @@ void k_rollout(const SolveDesc* __restrict__ descs,
       // obstacle row
       s_obs[threadIdx.x] = ObsL{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     }
-    // the window's loads all issued before the first store (4 per thread at
-    // 256 threads): one memory latency, not one per waypoint a thread stages
+    // the path window and (forms with fewer than eight lanes) the nominal
+    // inputs, 3T floats, their first loads all issued before the first store
+    // (the window's 4 per thread at 256 threads): one memory latency, not
+    // one per value a thread stages
+    const int R3 = 3 * (int)d.T, bd = (int)blockDim.x, tx = (int)threadIdx.x;
+    float un0 = 0.0f, un1 = 0.0f;
+    if constexpr (G < 8) {
+      un0 = gld(d.u_nom_in + min(tx, R3 - 1));
+      un1 = gld(d.u_nom_in + min(tx + bd, R3 - 1));
+    }
     for (int j0 = 0; j0 < nw; j0 += 4 * (int)blockDim.x) {
       float4 w[4];
 #pragma unroll
@@ -1685,6 +1774,11 @@ void k_rollout(const SolveDesc* __restrict__ descs,
         const int j = j0 + k * (int)blockDim.x + (int)threadIdx.x;
         if (j < nw) s_path[j] = make_float4(w[k].x - ox, w[k].y - oy, w[k].z, w[k].w);
       }
+    }
+    if constexpr (G < 8) {
+      if (tx < R3) s_unom[tx] = un0;
+      if (tx + bd < R3) s_unom[tx + bd] = un1;
+      for (int r = tx + 2 * bd; r < R3; r += bd) s_unom[r] = gld(d.u_nom_in + r);
     }
     // fused epilogue (direct launch of one instance): LDS for the tile's
     // applied inputs, costs (+inf where no sample stores), weights, units
@@ -1712,17 +1806,17 @@ void k_rollout(const SolveDesc* __restrict__ descs,
     bool done = false;
     if constexpr (GUIDED) {
       if (d.any_disc) {
-        rollout_sample<NOB, GUIDED, G, PRE, true, true>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+        rollout_sample<NOB, GUIDED, G, PRE, true, true>(d, s, valid && g == 0, g, x0, s_obs, s_path, s_unom, w0, nw, k0,
                                                         phi0, s_u, lds_stride, t_local, s_J);
         done = true;
       }
     }
     if (!done) {
       if (d.any_e4)
-        rollout_sample<NOB, GUIDED, G, PRE, true, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+        rollout_sample<NOB, GUIDED, G, PRE, true, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, s_unom, w0, nw, k0,
                                                          phi0, s_u, lds_stride, t_local, s_J);
       else
-        rollout_sample<NOB, GUIDED, G, PRE, false, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, w0, nw, k0,
+        rollout_sample<NOB, GUIDED, G, PRE, false, false>(d, s, valid && g == 0, g, x0, s_obs, s_path, s_unom, w0, nw, k0,
                                                           phi0, s_u, lds_stride, t_local, s_J);
     }
     __syncthreads();
