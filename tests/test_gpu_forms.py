@@ -294,6 +294,30 @@ def test_launch_shapes_bitwise_identical(ctx, n_obs, flags, e4):
     B.brmppi_set_launch(ctx.h, 0, 0)
 
 
+@pytest.mark.parametrize("T", [1, 2, 3, 7, 300])
+def test_horizons_odd_short_and_long_bitwise(ctx, T):
+    """the precomputed-normals forms step in pairs, the fewer-lane ones with an
+    odd last step peeled and the nominal inputs staged in LDS (3T floats, more
+    than two per thread at T = 300): every horizon gives the bits of the
+    one-lane in-kernel-noise form, which steps one at a time"""
+    p = W.random_small(91, S=1000, T=T, n_obs=9)
+    obs = p.obstacles.copy()
+    obs[1::3, 5] = 4.0
+    p = p.copy(obstacles=obs)
+    ctx.set_path(407, p.path, p.ds)
+    B.brmppi_set_launch(ctx.h, 64, 0)
+    ref = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=407), want_J=True, want_useq=True)
+    for variant in (1, 2, 3, 4):
+        for block in (64, 256):
+            log(f"  horizon T={T} block={block} variant={variant}")
+            B.brmppi_set_launch(ctx.h, block, variant)
+            g = B.brmppi_solve_ex(ctx.h, B.ProblemBuffers(p, controller=407), want_J=True, want_useq=True)
+            assert np.array_equal(g["J"], ref["J"]), (T, block, variant)
+            assert np.array_equal(g["useq"], ref["useq"]), (T, block, variant)
+            assert np.array_equal(g["U_new"], ref["U_new"]), (T, block, variant)
+    B.brmppi_set_launch(ctx.h, 0, 0)
+
+
 @pytest.mark.parametrize("block,variant", [(192, 0), (192, 2), (192, 3), (96 * 2, 4)])
 def test_block_192_many_groups(ctx, block, variant):
     """tiles of 192 samples (or 96, 48, 24 with lanes per sample) straddle the
