@@ -913,10 +913,12 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
     // refill below them.
     if constexpr (kLate) {
       asm volatile("" : "+v"(uj), "+v"(uw), "+v"(unu));
+      if constexpr (GUIDED) {
 #pragma unroll
-      for (int k = 0; k < NH; ++k) asm volatile("" : "+v"(at_h[k]));
+        for (int k = 0; k < NH; ++k) asm volatile("" : "+v"(at_h[k]));
 #pragma unroll
-      for (int j = 0; j < NSL; ++j) asm volatile("" : "+v"(at_o[j]));
+        for (int j = 0; j < NSL; ++j) asm volatile("" : "+v"(at_o[j]));
+      }
       __builtin_amdgcn_sched_barrier(0);
       load_normals(min(tau + 2, d.T - 1), q);
     }
