@@ -728,10 +728,10 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   constexpr int NBMAX = GUIDED ? (5 + NOB + 3) / 4 : 1;  // Philox blocks (fused noise)
   // a copy: the compiler keeps the parameters in registers instead of
   // re-reading the descriptor (a scalar load and a wait) inside the step
-  const brmppi_params P = d.prm;
-  const float t0 = d.t0, inv_ds = d.inv_ds;
-  const float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
-  const float inv_l1 = 1.0f / P.l1, inv_l2 = 1.0f / P.l2, ch = P.lh / P.l1;
+  brmppi_params P = d.prm;
+  float t0 = d.t0, inv_ds = d.inv_ds;
+  float Ts = P.Ts, Ts2 = P.Ts * P.Ts;
+  float inv_l1 = 1.0f / P.l1, inv_l2 = 1.0f / P.l2, ch = P.lh / P.l1;
   const int n_obs = (int)d.n_obs;
   const bool hitch = !(d.flags & BRMPPI_HITCH_OFF);
   // an unguided instance may share a guided launch: the flag is honoured here
@@ -752,9 +752,24 @@ __device__ __forceinline__ void rollout_sample(const SolveDesc& d, uint32_t s, b
   K.h_eps = P.h_eps;
   K.W_a = P.W_a;
   K.rho = P.rho;
-  const float Mj = P.W_j + P.rho, Mw = P.W_w + P.rho;
-  const float pj0 = 0.5f * P.rho * (P.j_lo + P.j_hi);
-  const float pw0 = 0.5f * P.rho * (P.w_lo + P.w_hi);
+  float Mj = P.W_j + P.rho, Mw = P.W_w + P.rho;
+  float pj0 = 0.5f * P.rho * (P.j_lo + P.j_hi);
+  float pw0 = 0.5f * P.rho * (P.w_lo + P.w_hi);
+  if constexpr (G == 8) {
+    // The eight-lane form has vector registers to spare (one wave per SIMD)
+    // and too few scalar ones: the step's constants are held in vector
+    // registers (an empty asm makes each a per-lane value), which frees the
+    // scalar registers that were spilled to vector lanes and re-read in
+    // every step, and saves the copies a scalar operand needs when an
+    // instruction already reads one.
+    auto vpin = [](float& x) { asm volatile("" : "+v"(x)); };
+    vpin(P.sigma_j); vpin(P.sigma_w); vpin(P.sigma_nu); vpin(P.sigma_a);
+    vpin(P.W_j); vpin(P.W_w); vpin(P.dtheta_max); vpin(P.kappa);
+    vpin(P.Qc); vpin(P.Ql); vpin(P.Qth1); vpin(P.Qth2); vpin(P.R_j); vpin(P.R_w); vpin(P.mu); vpin(P.nu_bar);
+    vpin(P.w_col); vpin(t0); vpin(inv_ds); vpin(Ts); vpin(Ts2); vpin(inv_l1); vpin(inv_l2); vpin(ch);
+    vpin(K.Ma); vpin(K.inv_Ma); vpin(K.amid); vpin(K.h_eps); vpin(K.W_a); vpin(K.rho);
+    vpin(Mj); vpin(Mw); vpin(pj0); vpin(pw0);
+  }
 
   float px = 0.0f, py = 0.0f, v = x0[2], a = x0[3], th1 = x0[4], th2 = x0[5], dl = x0[6], psi = 0.0f;
   float alpha_h[NH];
